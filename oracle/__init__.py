@@ -1,0 +1,211 @@
+"""CPU FP64 oracle for the AdS4 Einstein-Klein-Gordon method of lines.
+
+TEST INFRASTRUCTURE ONLY.  This package wraps ``liboracle.so`` (plain sequential
+C, see ``adscl_oracle.c``) with numpy.  Only ``tests/``, the package smoke check
+and the CPU-baseline leg of ``bench.py`` may import it.  The product library
+(``paper_1706_07413_amd``) never imports it and shares no code with it.
+
+All arrays are float64; one instance at a time.  Citations refer to Liebling &
+Khanna, arXiv:1706.07413 (Sec. II equations numbered as in the paper).
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GAUGE_BOUNDARY = 0
+GAUGE_ORIGIN = 1
+RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_p = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b  # noqa: F401  (build on first use in a checkout)
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "ora_tables": (None, [_i, _p, _p, _p, _p, _p]),
+        "ora_op_D": (None, [_i, _d, _p, _i, _i, _p]),
+        "ora_op_KO": (None, [_i, _d, _d, _p, _i, _i, _p]),
+        "ora_op_cell4": (None, [_i, _d, _p, _i, _i, _p]),
+        "ora_constraints": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
+        "ora_rhs": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p]),
+        "ora_evolve": (_i, [_i, _i, _i, _d, _d, _d, _p, _p, _i64, _i64, ctypes.c_int32, _i64, _p,
+                            _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
+        "ora_mass_paper": (_d, [_i, _p, _p, _p]),
+        "ora_residuals": (None, [_i, _p, _p, _p, _p, _p, _p]),
+        "ora_jacobi": (_d, [_i, _d, _d, _d]),
+        "ora_modes": (None, [_i, _i, _p, _p]),
+        "ora_spectrum": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
+        "ora_init_gaussian": (None, [_i, _d, _d, _p, _p]),
+        "ora_init_modes": (None, [_i, _d, _i, _p, _p, _p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def grid(N):
+    """x_i = i h, h = (pi/2)/(N-1)."""
+    h = (math.pi / 2) / (N - 1)
+    return np.arange(N) * h, h
+
+
+def dt_of(N, cfl=0.25):
+    return cfl * (math.pi / 2) / (N - 1)
+
+
+def n_steps_for(T, N, cfl=0.25):
+    """Number of steps to reach t >= T: ceil(T/dt - 1e-9); t_n = n dt is not clamped."""
+    return int(math.ceil(T / dt_of(N, cfl) - 1e-9))
+
+
+def tables(N):
+    lib = _load()
+    out = [np.empty(N) for _ in range(5)]
+    lib.ora_tables(N, *[_ptr(o) for o in out])
+    return dict(zip(["x", "sc", "t2", "ct2", "c3s"], out))
+
+
+def op_D(u, h, p0, p1):
+    lib = _load()
+    u = _f64(u)
+    out = np.empty_like(u)
+    lib.ora_op_D(len(u), h, _ptr(u), p0, p1, _ptr(out))
+    return out
+
+
+def op_KO(u, h, sig, p0, p1):
+    lib = _load()
+    u = _f64(u)
+    out = np.empty_like(u)
+    lib.ora_op_KO(len(u), h, sig, _ptr(u), p0, p1, _ptr(out))
+    return out
+
+
+def op_cell4(u, h, p0, p1):
+    lib = _load()
+    u = _f64(u)
+    out = np.empty(len(u) - 1)
+    lib.ora_op_cell4(len(u), h, _ptr(u), p0, p1, _ptr(out))
+    return out
+
+
+def constraints(Phi, Pi, gauge=GAUGE_BOUNDARY):
+    """Solve Eqs. (5)-(6) for one state; returns dict A, delta, m, dtil."""
+    lib = _load()
+    Phi, Pi = _f64(Phi), _f64(Pi)
+    N = len(Phi)
+    A, delta, m, dtil = (np.empty(N) for _ in range(4))
+    lib.ora_constraints(N, gauge, _ptr(Phi), _ptr(Pi), _ptr(A), _ptr(delta), _ptr(m), _ptr(dtil))
+    return dict(A=A, delta=delta, m=m, dtil=dtil)
+
+
+def rhs(Phi, Pi, A, delta, ko=0.5, frozen=False):
+    lib = _load()
+    Phi, Pi, A, delta = map(_f64, (Phi, Pi, A, delta))
+    N = len(Phi)
+    dPhi, dPi = np.empty(N), np.empty(N)
+    lib.ora_rhs(N, ko, int(frozen), _ptr(Phi), _ptr(Pi), _ptr(A), _ptr(delta), _ptr(dPhi), _ptr(dPi))
+    return dPhi, dPi
+
+
+def evolve(Phi, Pi, n_stop, n0=0, gauge=GAUGE_BOUNDARY, frozen=False, cfl=0.25, ko=0.5,
+           a_collapse=0.0, snap_every=0, n_slots=0, n_final=None):
+    """Evolve one instance from step n0 to n_stop (classical RK4, dt = cfl h).
+
+    Returns dict with Phi, Pi (state U^n at exit), A, delta, m (its metric),
+    steps (n at exit), state, minA, t, t_c and snaps [n_slots, 5, N] when
+    snap_every > 0.  State is DONE when n reaches ``n_final`` (default n_stop).
+    """
+    lib = _load()
+    Phi, Pi = _f64(Phi).copy(), _f64(Pi).copy()
+    N = len(Phi)
+    A, delta, m = np.empty(N), np.empty(N), np.empty(N)
+    snaps = np.zeros((max(n_slots, 1), 5, N))
+    n_out = _i64(0)
+    minA, tc = _d(0), _d(0)
+    st = lib.ora_evolve(N, gauge, int(frozen), cfl, ko, a_collapse, _ptr(Phi), _ptr(Pi),
+                        n0, n_stop, snap_every, n_slots, _ptr(snaps), _ptr(A), _ptr(delta), _ptr(m),
+                        ctypes.byref(n_out), ctypes.byref(minA), ctypes.byref(tc))
+    n_final = n_stop if n_final is None else n_final
+    if st == RUNNING and n_out.value >= n_final:
+        st = DONE
+    dt = dt_of(N, cfl)
+    return dict(Phi=Phi, Pi=Pi, A=A, delta=delta, m=m, steps=n_out.value, state=st,
+                minA=minA.value, t=n_out.value * dt, t_c=tc.value,
+                snaps=snaps[:n_slots] if n_slots > 0 else None)
+
+
+def mass_paper(Phi, Pi, A):
+    lib = _load()
+    Phi, Pi, A = map(_f64, (Phi, Pi, A))
+    return lib.ora_mass_paper(len(Phi), _ptr(Phi), _ptr(Pi), _ptr(A))
+
+
+def residuals(Phi, Pi, A, delta):
+    lib = _load()
+    Phi, Pi, A, delta = map(_f64, (Phi, Pi, A, delta))
+    N = len(Phi)
+    RA, Rd = np.empty(N), np.empty(N)
+    lib.ora_residuals(N, _ptr(Phi), _ptr(Pi), _ptr(A), _ptr(delta), _ptr(RA), _ptr(Rd))
+    return RA, Rd
+
+
+def jacobi(n, a, b, z):
+    return _load().ora_jacobi(n, a, b, z)
+
+
+def modes(N, J):
+    lib = _load()
+    e, de = np.empty((J, N)), np.empty((J, N))
+    lib.ora_modes(N, J, _ptr(e), _ptr(de))
+    return e, de
+
+
+def spectrum(Phi, Pi, A, J):
+    lib = _load()
+    Phi, Pi, A = map(_f64, (Phi, Pi, A))
+    N = len(Phi)
+    E, Ph, Fh = np.empty(J), np.empty(J), np.empty(J)
+    lib.ora_spectrum(N, J, _ptr(Phi), _ptr(Pi), _ptr(A), _ptr(E), _ptr(Ph), _ptr(Fh))
+    return E, Ph, Fh
+
+
+def init_gaussian(N, eps, sigma):
+    lib = _load()
+    Phi, Pi = np.empty(N), np.empty(N)
+    lib.ora_init_gaussian(N, eps, sigma, _ptr(Phi), _ptr(Pi))
+    return Phi, Pi
+
+
+def init_modes(N, eps, c):
+    lib = _load()
+    c = _f64(c)
+    Phi, Pi = np.empty(N), np.empty(N)
+    lib.ora_init_modes(N, eps, len(c), _ptr(c), _ptr(Phi), _ptr(Pi))
+    return Phi, Pi
