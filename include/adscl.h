@@ -1,0 +1,146 @@
+/*
+ * adscl.h -- C ABI of the MI355X (gfx950) library that evolves spherically
+ * symmetric scalar collapse in asymptotically AdS4 (Liebling & Khanna,
+ * arXiv:1706.07413, Sec. II) for a batch of independent instances.
+ *
+ * Method (Sec. II): fields Phi = phi', Pi = e^delta phi_dot / A on the compactified
+ * radius x in [0, pi/2]; Eqs. (2)-(3) evolved by the method of lines (classical
+ * RK4, dt = cfl * h, 4th-order centred differences plus 6th-difference
+ * Kreiss-Oliger dissipation, parity ghosts at both ends); the metric functions A
+ * and delta re-derived from the constraints Eqs. (5)-(6) at every stage, as two
+ * prefix integrals over the grid.  All arithmetic is FP64.
+ *
+ * Layout: instance b has an odd grid size N_b (17 <= N_b <= 4097), h_b =
+ * (pi/2)/(N_b-1), x_i = i h_b.  Every per-point array is packed: instance b
+ * occupies [off_b, off_b + N_b) with off_b the exclusive prefix sum of N_b, in
+ * the order the instances were given to adscl_create.
+ *
+ * Ownership: the context owns all device memory it allocates.  Pointers passed
+ * in are borrowed for the duration of the call only.  Output buffers are
+ * allocated by the caller.  `mem` says whether a pointer is host memory
+ * (ADSCL_MEM_HOST) or device memory of the context's GPU (ADSCL_MEM_DEVICE).
+ *
+ * Asynchrony: work is enqueued on the context's stream.  A call that writes to
+ * a host pointer synchronises that stream before it returns; calls with device
+ * pointers only enqueue work (use adscl_sync).
+ *
+ * Errors: every int-returning call returns ADSCL_OK (0) or a negative code;
+ * adscl_last_error gives the message.  Nothing throws across the ABI.  Collapse
+ * and non-finite data are per-instance states, not errors.  A context is not
+ * thread-safe; distinct contexts are independent.
+ */
+#ifndef ADSCL_H
+#define ADSCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adscl_ctx adscl_ctx;
+
+enum {
+    ADSCL_OK = 0,
+    ADSCL_EINVAL = -1,       /* bad argument (sizes, pointers, ranges)          */
+    ADSCL_ENOMEM = -2,       /* device allocation failed                         */
+    ADSCL_EHIP = -3,         /* a HIP runtime call failed                        */
+    ADSCL_ESTATE = -4,       /* call order, e.g. step before any init            */
+    ADSCL_EUNSUPPORTED = -5  /* valid request this build cannot serve            */
+};
+
+/* Gauge of delta: boundary time delta(pi/2,t) = 0 (Sec. II, Eq. (12)), or
+ * delta(0,t) = 0 (proper time at the origin). */
+enum { ADSCL_GAUGE_BOUNDARY = 0, ADSCL_GAUGE_ORIGIN = 1 };
+enum { ADSCL_MEM_HOST = 0, ADSCL_MEM_DEVICE = 1 };
+/* Flags: hold A = 1 and delta = 0 instead of solving the constraints (the
+ * fixed-metric case of Sec. IV.C, Table II). */
+enum { ADSCL_FROZEN_METRIC = 1 };
+/* Per-instance states.  COLLAPSED: min_i A_i < a_collapse at the start of a step
+ * (Sec. II, collapse when min A becomes small); NONFINITE: a non-finite Phi, Pi,
+ * A or delta at the start of a step; DONE: reached the requested end time. */
+enum { ADSCL_RUNNING = 0, ADSCL_COLLAPSED = 1, ADSCL_NONFINITE = 2, ADSCL_DONE = 3 };
+
+typedef struct {
+    int32_t n_inst;          /* number of instances, >= 1                            */
+    const int32_t* n_grid;   /* host [n_inst]: N_b, odd, 17 <= N_b <= 4097            */
+    double cfl;              /* dt = cfl * h_b; default 0.25                          */
+    double ko_sigma;         /* Kreiss-Oliger coefficient; default 0.5                */
+    double a_collapse;       /* collapse threshold on min A (paper: 0.01)             */
+    int32_t gauge;           /* ADSCL_GAUGE_*                                         */
+    int32_t n_modes;         /* largest J for adscl_spectrum / adscl_init_modes, <=128 */
+    int32_t flags;           /* ADSCL_FROZEN_METRIC or 0                              */
+} adscl_config;
+
+/* Create a context on the current HIP device.  `hip_stream` is a hipStream_t
+ * to enqueue on, or NULL for a stream the context creates and owns.  Validates
+ * the whole configuration before touching the GPU (bad N -> ADSCL_EINVAL). */
+int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out);
+void adscl_destroy(adscl_ctx* ctx);
+
+/* Initial data, Sec. II: Phi(x,0), Pi(x,0) are given and the constraints
+ * Eqs. (5)-(6) are solved at t = 0.  Each init resets every instance to step 0
+ * and state RUNNING, enforces the pinned values Phi_0 = Phi_{N-1} = Pi_{N-1} = 0
+ * (Eqs. (7), (9)-(10)), solves the constraints, and flags instances that are
+ * collapsed or non-finite already at t = 0. */
+/* Phi0, Pi0: packed [sum N_b]. */
+int adscl_init(adscl_ctx* ctx, const double* Phi0, const double* Pi0, int mem);
+/* Pi(x,0) = (2 eps_b/pi) exp(-4 tan^2 x / (pi^2 sigma_b^2)), Phi(x,0) = 0.
+ * eps, sigma: [n_inst]. */
+int adscl_init_gaussian(adscl_ctx* ctx, const double* eps, const double* sigma, int mem);
+/* Pi(x,0) = eps_b sum_{j<Jc} c_{b,j} e_j(x), Phi(x,0) = 0, with the linear AdS4
+ * eigenmodes e_j(x) = d_j cos^3 x P_j^(1/2,3/2)(cos 2x), unit norm in
+ * int_0^{pi/2} f g tan^2 x dx (Sec. II: data defined from a mode spectrum).
+ * eps: [n_inst]; c: [n_inst x Jc] row-major; 1 <= Jc <= n_modes. */
+int adscl_init_modes(adscl_ctx* ctx, const double* eps, const double* c, int32_t Jc, int mem);
+
+/* Advance every RUNNING (or DONE) instance b from its current step n_b to
+ * min(n_b + max_steps, n_final_b), n_final_b = ceil(t_end / dt_b - 1e-9);
+ * t_n = n dt_b.  At the start of each step (and at the stop step) the
+ * constraints of the current state are solved and the collapse / non-finite
+ * tests applied; a flagged instance stops where it is.  Instances reaching
+ * n_final_b become DONE.  max_steps >= 0 (0 only re-solves the constraints).
+ * Snapshots: when snap_every > 0 and n is a multiple of snap_every with slot
+ * n / snap_every < n_snap_slots, (Phi, Pi, A, delta, m) of step n are written
+ * to snaps[slot][field][sum N_b] (5 fields, m the mass function
+ * (1-A) sin x / cos^3 x).  snaps may be NULL when snap_every == 0. */
+int adscl_step(adscl_ctx* ctx, int64_t max_steps, double t_end, int32_t snap_every,
+               int32_t n_snap_slots, double* snaps, int mem);
+
+/* Current state U^n of every instance and its metric: Phi, Pi, A, delta, m
+ * (each packed [sum N_b], any may be NULL). */
+int adscl_get_state(adscl_ctx* ctx, double* Phi, double* Pi, double* A, double* delta, double* m, int mem);
+
+/* Host arrays [n_inst], any may be NULL: t_n, step n, state, t at
+ * collapse/non-finite (-1 if none), min A of the current state. */
+int adscl_status(adscl_ctx* ctx, double* t, int64_t* steps, int32_t* state, double* t_collapse, double* minA);
+
+/* Diagnostics of the current state (Sec. II: mass and constraint residuals),
+ * out [n_inst x 4]: max_i |R_A'|, max_i |R_delta'| over interior points with
+ * R_A' = D A - [(1+2 sin^2 x)/(sin x cos x)(1-A) - sin x cos x A (Phi^2+Pi^2)]
+ * (Eq. (5)) and R_delta' = D delta + sin x cos x (Phi^2+Pi^2) (Eq. (6)), the
+ * mass m(pi/2), and M = int tan^2 x A (Phi^2+Pi^2) dx by 4-point cell rule. */
+int adscl_constraints(adscl_ctx* ctx, double* out, int mem);
+
+/* Mode energies of the current state (Sec. II: decomposition into normal
+ * modes), J <= n_modes, outputs [n_inst x J] (any may be NULL):
+ * Pihat_j = sum_i h tan^2 x_i e_j(x_i) sqrt(A_i) Pi_i,
+ * Phihat_j = sum_i h tan^2 x_i e_j'(x_i)/omega_j sqrt(A_i) Phi_i (interior i),
+ * omega_j = 3 + 2j, E_j = Pihat_j^2 + Phihat_j^2.  Instances whose min A < 0
+ * give NaN. */
+int adscl_spectrum(adscl_ctx* ctx, int32_t J, double* E, double* Pihat, double* Phihat, int mem);
+
+/* Block until all work enqueued on the context's stream is done. */
+int adscl_sync(adscl_ctx* ctx);
+
+/* Packed offsets off_b (host [n_inst]) and the total sum N_b. */
+int adscl_layout(const adscl_ctx* ctx, int64_t* off, int64_t* total);
+
+/* Message of the last failed call on this context (or of the last failed
+ * adscl_create when ctx is NULL); valid until the next call. */
+const char* adscl_last_error(const adscl_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADSCL_H */

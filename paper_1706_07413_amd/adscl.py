@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libadscl.so (include/adscl.h).
+
+Argument marshalling only: every step of the evolution runs in the HIP kernels
+of the library.  Device arrays are torch tensors on the context's GPU (their
+data pointers go straight through the ABI); host arrays are numpy arrays.  The
+module refuses to work without the built library.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadscl.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GAUGE_BOUNDARY, GAUGE_ORIGIN = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+FROZEN_METRIC = 1
+RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
+
+# Every function include/adscl.h declares.
+EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
+           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum",
+           "adscl_sync", "adscl_layout", "adscl_last_error")
+
+
+class AdsclError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("adscl error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("n_grid", ctypes.POINTER(ctypes.c_int32)),
+                ("cfl", ctypes.c_double), ("ko_sigma", ctypes.c_double), ("a_collapse", ctypes.c_double),
+                ("gauge", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+
+
+def lib():
+    """Load libadscl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libadscl.so is not built (%s); run python -m paper_1706_07413_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "adscl_create": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.POINTER(_vp)]),
+        "adscl_destroy": (None, [_vp]),
+        "adscl_init": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+        "adscl_init_gaussian": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+        "adscl_init_modes": (ctypes.c_int, [_vp, _vp, _vp, _i32, ctypes.c_int]),
+        "adscl_step": (ctypes.c_int, [_vp, _i64, _d, _i32, _i32, _vp, ctypes.c_int]),
+        "adscl_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int]),
+        "adscl_status": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "adscl_constraints": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+        "adscl_spectrum": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_int]),
+        "adscl_sync": (ctypes.c_int, [_vp]),
+        "adscl_layout": (ctypes.c_int, [_vp, _vp, _vp]),
+        "adscl_last_error": (ctypes.c_char_p, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr_mem(a):
+    """(pointer, mem) of a torch tensor (device) or numpy array (host)."""
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError("host arrays must be C-contiguous float64")
+        return a.ctypes.data, MEM_HOST
+    import torch
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError("tensors must be contiguous float64")
+        return a.data_ptr(), (MEM_DEVICE if a.is_cuda else MEM_HOST)
+    raise TypeError("expected numpy array or torch tensor")
+
+
+class Batch:
+    """A batch of independent instances with grid sizes ``n_grid`` on one GPU."""
+
+    def __init__(self, n_grid, cfl=0.25, ko_sigma=0.5, a_collapse=0.01, gauge=GAUGE_BOUNDARY, n_modes=0,
+                 flags=0, stream=None):
+        L = lib()
+        self._N = np.ascontiguousarray(np.asarray(n_grid, dtype=np.int32))
+        cfg = Config(len(self._N), self._N.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cfl, ko_sigma,
+                     a_collapse, gauge, n_modes, flags)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = _vp()
+        rc = L.adscl_create(ctypes.byref(cfg), _vp(stream), ctypes.byref(h))
+        if rc != OK:
+            raise AdsclError(rc, L.adscl_last_error(None).decode())
+        self._h = h
+        self.n_inst = len(self._N)
+        self.cfl = cfl
+        off = np.zeros(self.n_inst, np.int64)
+        tot = _i64(0)
+        L.adscl_layout(self._h, off.ctypes.data, ctypes.byref(tot))
+        self.off = off
+        self.total = tot.value
+        self.n_grid = self._N
+
+    def _check(self, rc):
+        if rc != OK:
+            raise AdsclError(rc, lib().adscl_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().adscl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- initial data ----
+    def init(self, Phi0, Pi0):
+        p1, m1 = _ptr_mem(Phi0)
+        p2, m2 = _ptr_mem(Pi0)
+        assert m1 == m2
+        self._check(lib().adscl_init(self._h, p1, p2, m1))
+
+    def init_gaussian(self, eps, sigma):
+        p1, m1 = _ptr_mem(eps)
+        p2, m2 = _ptr_mem(sigma)
+        assert m1 == m2
+        self._check(lib().adscl_init_gaussian(self._h, p1, p2, m1))
+
+    def init_modes(self, eps, c):
+        p1, m1 = _ptr_mem(eps)
+        p2, m2 = _ptr_mem(c)
+        assert m1 == m2
+        self._check(lib().adscl_init_modes(self._h, p1, p2, int(c.shape[1]), m1))
+
+    # ---- evolution ----
+    def step(self, max_steps, t_end, snap_every=0, snaps=None):
+        """Advance; ``snaps`` (optional) is a [slots, 5, total] float64 array/tensor."""
+        if snaps is not None:
+            p, m = _ptr_mem(snaps)
+            slots = int(snaps.shape[0])
+        else:
+            p, m, slots = None, MEM_DEVICE, 0
+        self._check(lib().adscl_step(self._h, int(max_steps), float(t_end), int(snap_every), slots, p, m))
+        if snaps is not None and m == MEM_DEVICE:
+            self.sync()
+
+    def sync(self):
+        self._check(lib().adscl_sync(self._h))
+
+    # ---- outputs ----
+    def get_state(self, out=None):
+        """Dict of packed Phi, Pi, A, delta, m (torch tensors on the GPU unless
+        ``out`` holds numpy arrays)."""
+        if out is None:
+            import torch
+            out = {k: torch.empty(self.total, dtype=torch.float64, device="cuda")
+                   for k in ("Phi", "Pi", "A", "delta", "m")}
+        ptrs = [_ptr_mem(out[k]) for k in ("Phi", "Pi", "A", "delta", "m")]
+        mem = ptrs[0][1]
+        self._check(lib().adscl_get_state(self._h, *[p for p, _ in ptrs], mem))
+        if mem == MEM_DEVICE:
+            # the context's stream is not ordered with torch's streams
+            self.sync()
+        return out
+
+    def status(self):
+        n = self.n_inst
+        t, tc, mA = np.zeros(n), np.zeros(n), np.zeros(n)
+        steps = np.zeros(n, np.int64)
+        state = np.zeros(n, np.int32)
+        self._check(lib().adscl_status(self._h, t.ctypes.data, steps.ctypes.data, state.ctypes.data,
+                                       tc.ctypes.data, mA.ctypes.data))
+        return dict(t=t, steps=steps, state=state, t_c=tc, minA=mA)
+
+    def constraints(self):
+        out = np.zeros((self.n_inst, 4))
+        self._check(lib().adscl_constraints(self._h, out.ctypes.data, MEM_HOST))
+        return out
+
+    def spectrum(self, J):
+        E, P, F = (np.zeros((self.n_inst, J)) for _ in range(3))
+        self._check(lib().adscl_spectrum(self._h, int(J), E.ctypes.data, P.ctypes.data, F.ctypes.data, MEM_HOST))
+        return E, P, F
+
+    def split(self, packed):
+        """List of per-instance views of a packed array."""
+        return [packed[o:o + n] for o, n in zip(self.off, self.n_grid)]

@@ -1,0 +1,254 @@
+"""Parity of the HIP library (through the C ABI) with the CPU FP64 oracle.
+
+Every comparison runs the same seeded inputs through both sides and compares
+element by element: the relative max-norm ||u_gpu - u_ora|| / ||u_ora|| of each
+field must be <= 1e-11 (absolute 1e-13 for a field whose oracle norm is below
+1e-12, e.g. Phi at t = 0).  Integer outputs (steps, states) must match exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1706_07413_amd import adscl
+from paper_1706_07413_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+FIELDS = ("Phi", "Pi", "A", "delta", "m")
+
+
+def rel(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    n = np.max(np.abs(o)) if o.size else 0.0
+    d = np.max(np.abs(g - o)) if o.size else 0.0
+    if n < 1e-12:
+        return d / 1e-13 * TOL  # absolute 1e-13 maps onto the tolerance
+    return d / n
+
+
+def assert_close(g, o, what):
+    e = rel(g, o)
+    assert e <= TOL, "%s: relative max-norm error %.3e" % (what, e)
+
+
+def gpu_state(b):
+    s = b.get_state()
+    return {k: v.cpu().numpy() for k, v in s.items()}
+
+
+def oracle_gauss(N, eps, sig, n_stop, gauge=O.GAUGE_BOUNDARY, **kw):
+    Phi, Pi = O.init_gaussian(N, eps, sig)
+    return O.evolve(Phi, Pi, n_stop, gauge=gauge, **kw)
+
+
+def compare_instance(batch, st, b, ref, what):
+    for f in FIELDS:
+        assert_close(batch.split(st[f])[b], ref[f if f not in ("Phi", "Pi") else f], "%s %s" % (what, f))
+
+
+# --------------------------------------------------------------------------
+
+def test_config0_full_run_with_snapshots():
+    """N=513 Gaussian (eps=10, sigma=1/16), origin gauge, 8192 steps to t=2 pi,
+    (Phi, Pi, A, delta, m) every 256 steps: all 33 snapshots."""
+    import torch
+    c = I.config0()
+    N = int(c["N"][0])
+    n = O.n_steps_for(c["T"], N)
+    assert n == 8192
+    b = adscl.Batch(c["N"], gauge=c["gauge"], a_collapse=c["a_collapse"])
+    b.init_gaussian(c["eps"], c["sigma"])
+    snaps = torch.zeros((33, 5, b.total), dtype=torch.float64, device="cuda")
+    b.step(n, c["T"], snap_every=256, snaps=snaps)
+    st = b.status()
+    assert st["steps"][0] == n and st["state"][0] == adscl.DONE
+    Phi, Pi = O.init_gaussian(N, float(c["eps"][0]), float(c["sigma"][0]))
+    ref = O.evolve(Phi, Pi, n, gauge=c["gauge"], a_collapse=c["a_collapse"], snap_every=256, n_slots=33)
+    g = snaps.cpu().numpy()
+    for s in range(33):
+        for f in range(5):
+            assert_close(g[s, f], ref["snaps"][s, f], "snapshot %d field %s" % (s, FIELDS[f]))
+    assert abs(st["minA"][0] - ref["minA"]) < 1e-12
+
+
+@pytest.mark.parametrize("gauge", [O.GAUGE_BOUNDARY, O.GAUGE_ORIGIN])
+def test_ragged_batch_small_sizes(gauge):
+    """Mixed grid sizes in one batch, including sizes that do not fill a lane
+    block (ragged tails), 300 steps each."""
+    Ns = [17, 33, 65, 101, 129, 257, 301, 513, 777, 1025, 1999, 2049]
+    rng = np.random.default_rng(5)
+    eps = rng.uniform(1.0, 8.0, len(Ns))
+    sig = rng.uniform(0.1, 0.3, len(Ns))
+    b = adscl.Batch(Ns, gauge=gauge, a_collapse=0.0)
+    b.init_gaussian(eps, sig)
+    b.step(300, 1e9)
+    st = gpu_state(b)
+    s = b.status()
+    for i, N in enumerate(Ns):
+        ref = oracle_gauss(N, eps[i], sig[i], 300, gauge=gauge)
+        assert s["steps"][i] == 300 and s["state"][i] == adscl.RUNNING
+        compare_instance(b, st, i, ref, "N=%d" % N)
+
+
+def test_config2_seeded_subset():
+    """The first 12 instances of the 1024-instance workload (N in {1025, 2049,
+    4097}), 200 steps; collapse threshold 0.02."""
+    c = I.config2(12)
+    b = adscl.Batch(c["N"], gauge=c["gauge"], a_collapse=c["a_collapse"])
+    b.init_gaussian(c["eps"], c["sigma"])
+    b.step(200, c["T"])
+    st = gpu_state(b)
+    s = b.status()
+    for i in range(12):
+        ref = oracle_gauss(int(c["N"][i]), c["eps"][i], c["sigma"][i], 200, gauge=c["gauge"],
+                           a_collapse=c["a_collapse"])
+        assert s["steps"][i] == ref["steps"], i
+        assert s["state"][i] == (ref["state"] if ref["state"] != O.DONE else adscl.RUNNING), i
+        compare_instance(b, st, i, ref, "inst %d N=%d" % (i, c["N"][i]))
+
+
+def test_frozen_metric():
+    Ns = [129, 1025]
+    c = np.array([[1.0, -0.5, 0.25, 0.1], [0.3, 0.2, -0.7, 0.05]])
+    b = adscl.Batch(Ns, n_modes=4, flags=adscl.FROZEN_METRIC)
+    b.init_modes(np.ones(2), c)
+    b.step(400, 1e9)
+    st = gpu_state(b)
+    for i, N in enumerate(Ns):
+        Phi, Pi = O.init_modes(N, 1.0, c[i])
+        ref = O.evolve(Phi, Pi, 400, frozen=True)
+        for f in ("Phi", "Pi"):
+            assert_close(b.split(st[f])[i], ref[f], "frozen N=%d %s" % (N, f))
+        assert np.all(b.split(st["A"])[i] == 1.0)
+
+
+def test_mode_data_and_spectrum():
+    """Mode-sum initial data (32 modes, c_j ~ N(0,1) e^{-j/4}, eps=0.1) and the
+    16-mode spectrum, at t = 0 and after 500 steps."""
+    c = I.config3()
+    Ns = [1025, 4097]
+    coef = np.repeat(c["c"], 2, axis=0)
+    eps = np.array([0.1, 0.1])
+    b = adscl.Batch(Ns, n_modes=32)
+    b.init_modes(eps, coef)
+    for nsteps in (0, 500):
+        if nsteps:
+            b.step(nsteps, 1e9)
+        st = gpu_state(b)
+        E, Ph, Fh = b.spectrum(16)
+        for i, N in enumerate(Ns):
+            Phi, Pi = O.init_modes(N, 0.1, coef[i])
+            ref = O.evolve(Phi, Pi, nsteps)
+            compare_instance(b, st, i, ref, "modes N=%d n=%d" % (N, nsteps))
+            Eo, Po, Fo = O.spectrum(ref["Phi"], ref["Pi"], ref["A"], 16)
+            assert_close(E[i], Eo, "E N=%d" % N)
+            assert_close(Ph[i], Po, "Pihat N=%d" % N)
+            if nsteps:
+                assert_close(Fh[i], Fo, "Phihat N=%d" % N)
+
+
+def test_constraints_diagnostics_match_oracle():
+    Ns = [257, 1025]
+    b = adscl.Batch(Ns)
+    b.init_gaussian(np.array([4.0, 6.0]), np.array([0.25, 0.2]))
+    b.step(100, 1e9)
+    st = gpu_state(b)
+    out = b.constraints()
+    for i, N in enumerate(Ns):
+        Phi, Pi, A, d = (b.split(st[f])[i] for f in ("Phi", "Pi", "A", "delta"))
+        RA, Rd = O.residuals(Phi, Pi, A, d)
+        # a residual is a difference of O(1) terms: compare on the scale of the terms
+        x, h = O.grid(N)
+        xi = x[1:-1]
+        sc = np.sin(xi) * np.cos(xi)
+        q = (Phi ** 2 + Pi ** 2)[1:-1]
+        scale_d = np.max(np.abs(sc * q))
+        scale_A = np.max(np.abs((1 + 2 * np.sin(xi) ** 2) / sc * (1 - A[1:-1]))) + np.max(np.abs(sc * A[1:-1] * q))
+        assert abs(out[i, 0] - np.max(np.abs(RA))) <= 1e-11 * scale_A
+        assert abs(out[i, 1] - np.max(np.abs(Rd))) <= 1e-11 * scale_d
+        assert abs(out[i, 2] - b.split(st["m"])[i][-1]) == 0.0
+        assert abs(out[i, 3] - O.mass_paper(Phi, Pi, A)) <= 1e-12 * out[i, 3]
+
+
+def test_collapse_and_failure_states():
+    """Per-instance states: a collapsing instance stops at the oracle's step, an
+    instance with NaN data is flagged non-finite at t = 0, an instance born
+    below the threshold is collapsed at t = 0, and the others are unaffected."""
+    N = 257
+    eps = np.array([20.0, 1.0, 100.0, 2.0])
+    sig = np.array([0.1, 0.25, 0.15, 0.2])
+    b = adscl.Batch([N] * 4, a_collapse=0.05)
+    Phi0 = np.zeros(4 * N)
+    Pi0 = np.concatenate([O.init_gaussian(N, e, s)[1] for e, s in zip(eps, sig)])
+    Pi0[N + 40] = np.nan
+    b.init(Phi0, Pi0)
+    s = b.status()
+    assert list(s["state"]) == [adscl.RUNNING, adscl.NONFINITE, adscl.COLLAPSED, adscl.RUNNING]
+    b.step(20000, 1e9)
+    s = b.status()
+    ref0 = oracle_gauss(N, eps[0], sig[0], 20000, a_collapse=0.05)
+    assert ref0["state"] == O.COLLAPSED
+    assert s["state"][0] == adscl.COLLAPSED
+    assert abs(int(s["steps"][0]) - ref0["steps"]) <= 1  # ties at the threshold
+    assert s["steps"][1] == 0 and s["steps"][2] == 0
+    ref3 = oracle_gauss(N, eps[3], sig[3], 20000, a_collapse=0.05)
+    assert s["steps"][3] == ref3["steps"]
+    st = gpu_state(b)
+    compare_instance(b, st, 3, ref3, "unaffected neighbour")
+
+
+def test_zero_steps_and_resume_equal_one_call():
+    """max_steps = 0 leaves the state untouched; three chunks of steps give the
+    same bits as one call."""
+    Ns = [513, 1025]
+    eps, sig = np.array([5.0, 3.0]), np.array([0.2, 0.25])
+    b1 = adscl.Batch(Ns)
+    b1.init_gaussian(eps, sig)
+    st0 = gpu_state(b1)
+    b1.step(0, 1e9)
+    assert all(np.array_equal(st0[f], gpu_state(b1)[f]) for f in FIELDS)
+    for _ in range(3):
+        b1.step(70, 1e9)
+    b2 = adscl.Batch(Ns)
+    b2.init_gaussian(eps, sig)
+    b2.step(210, 1e9)
+    s1, s2 = gpu_state(b1), gpu_state(b2)
+    for f in FIELDS:
+        assert np.array_equal(s1[f], s2[f]), f
+
+
+def test_batched_equals_single_instance_bitwise():
+    c = I.config2(6)
+    b = adscl.Batch(c["N"], a_collapse=c["a_collapse"])
+    b.init_gaussian(c["eps"], c["sigma"])
+    b.step(64, c["T"])
+    sb = gpu_state(b)
+    for i in range(6):
+        s1 = adscl.Batch(c["N"][i:i + 1], a_collapse=c["a_collapse"])
+        s1.init_gaussian(c["eps"][i:i + 1], c["sigma"][i:i + 1])
+        s1.step(64, c["T"])
+        ss = gpu_state(s1)
+        for f in FIELDS:
+            assert np.array_equal(b.split(sb[f])[i], ss[f]), (i, f)
+
+
+def test_full_size_workload_launch_sampled():
+    """The 1024-instance workload in the launch configuration the benchmark
+    uses, 32 steps; a sample of instances of each grid size vs the oracle."""
+    c = I.config2()
+    b = adscl.Batch(c["N"], gauge=c["gauge"], a_collapse=c["a_collapse"])
+    b.init_gaussian(c["eps"], c["sigma"])
+    b.step(32, c["T"])
+    st = gpu_state(b)
+    s = b.status()
+    assert np.all(s["steps"] == 32)
+    picks = []
+    for N in (1025, 2049, 4097):
+        idx = np.nonzero(c["N"] == N)[0]
+        picks += [int(idx[0]), int(idx[-1])]
+    for i in picks:
+        ref = oracle_gauss(int(c["N"][i]), c["eps"][i], c["sigma"][i], 32, a_collapse=c["a_collapse"])
+        compare_instance(b, st, i, ref, "inst %d" % i)
