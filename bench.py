@@ -1,0 +1,191 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the batched AdS4 scalar-collapse evolution on one MI355X.
+
+Workload (seeded, synthetic): 1024 independent instances of Gaussian initial
+data, sigma ~ U[1/16, 1/4], eps log-uniform in [1, 40], grid sizes drawn from
+{1025, 2049, 4097}, classical RK4 with dt = h/4, evolved to t = 50 or until
+min A < 0.02, boundary-time gauge.  One benchmark step is one complete pass over
+that batch: initial data and t = 0 constraint solve, then the evolution of every
+instance to its end (or collapse), all on the GPU.
+
+Metric: FP64 grid-point RK4 updates per second (one grid point advanced one
+full RK4 step), counting only steps actually taken by instances that have not
+collapsed.  Printed as one JSON line, with the roofline of the dominant kernel
+launch and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "FP64 grid-point RK4 updates/s, batched vs single-instance; adjoint grads/s"
+UNIT = "grid-point RK4 updates/s"
+# Algorithmic work per grid point per RK4 stage of the scheme:
+# 76 FP64 add/mul/fma-terms of the constraint scans, fluxes, D and KO stencils
+# and RK combination, plus one exp counted at 24 flops.
+FLOP_PER_PT_STAGE = 100.0
+BYTES_PER_PT_STEP = 32.0          # read (Phi, Pi)^n, write (Phi, Pi)^{n+1}
+PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def pt_steps(N, steps):
+    return float(np.sum(np.asarray(N, np.float64) * np.asarray(steps, np.float64)))
+
+
+def cpu_baseline(cfg, seconds):
+    """The oracle, single-threaded, on the first instances of the workload for a
+    fixed number of steps each, until about `seconds` of CPU work is done."""
+    import oracle as O
+    work, t_used, n_inst = 0.0, 0.0, 0
+    steps = 256
+    t0 = time.perf_counter()
+    for i in range(len(cfg["N"])):
+        N = int(cfg["N"][i])
+        Phi, Pi = O.init_gaussian(N, float(cfg["eps"][i]), float(cfg["sigma"][i]))
+        r = O.evolve(Phi, Pi, steps, gauge=cfg["gauge"], a_collapse=cfg["a_collapse"])
+        work += N * r["steps"]
+        n_inst += 1
+        t_used = time.perf_counter() - t0
+        if t_used >= seconds:
+            break
+    return dict(value=work / t_used, unit=UNIT, cores=1, kind="oracle",
+                sample="first %d instances of the 1024-instance workload, %d RK4 steps each, "
+                       "oracle (gcc -O2, 1 thread)" % (n_inst, steps))
+
+
+def single_instance_rates(adscl, steps):
+    """Rate of one instance alone on the GPU (same kernel path), per grid size."""
+    import torch
+    rates = {}
+    for N in (1025, 2049, 4097):
+        b = adscl.Batch([N], a_collapse=0.02)
+        eps = torch.tensor([2.0], dtype=torch.float64, device="cuda")
+        sig = torch.tensor([0.2], dtype=torch.float64, device="cuda")
+        b.init_gaussian(eps, sig)
+        b.step(64, 1e9)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(steps, 1e9)
+        b.sync()
+        dt = time.perf_counter() - t0
+        rates[N] = N * steps / dt
+        b.close()
+    return rates
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed passes over the batch")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--t-end", type=float, default=5.0,
+                    help="end time of every pass (the workload's full run is 50)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the workload, run a plain device copy of this many bytes "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        n = args.copy_bytes // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "dispatches": 3}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: every box here has a single MI355X and the batch is not "
+              "sharded across GPUs (instances are independent; see DESIGN.md for the sharding plan).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1706_07413_amd import adscl
+    from paper_1706_07413_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    cfg = I.config2()
+    T = args.t_end
+    eps = torch.tensor(cfg["eps"], dtype=torch.float64, device="cuda")
+    sig = torch.tensor(cfg["sigma"], dtype=torch.float64, device="cuda")
+    batch = adscl.Batch(cfg["N"], gauge=cfg["gauge"], a_collapse=cfg["a_collapse"], flags=adscl.TIME_KERNELS)
+
+    def one_pass():
+        batch.init_gaussian(eps, sig)
+        batch.step(1 << 40, T)
+        batch.sync()
+        return batch.status()
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    work = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = one_pass()
+        work += pt_steps(cfg["N"], st["steps"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = work / elapsed
+
+    # roofline of the dominant launch (longest class launch of the last pass)
+    classes, cls = batch.kernel_stats()
+    k = int(np.argmax([c["last_ms"] for c in classes]))
+    mem = cls == k
+    unit_steps = pt_steps(np.asarray(cfg["N"])[mem], st["steps"][mem])
+    ms = classes[k]["last_ms"]
+    achieved = unit_steps * 4 * FLOP_PER_PT_STAGE / (ms * 1e-3) / 1e12
+    states = np.bincount(st["state"], minlength=4)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched_gaussian_1024: 1024 instances, N in {1025,2049,4097}, "
+                               "eps log-U[1,40], sigma U[1/16,1/4], RK4 dt=h/4, t_end=%g, collapse min A<0.02" % T,
+                   "instances": int(len(cfg["N"])), "t_end": T,
+                   "pt_steps_per_pass": work / args.steps,
+                   "collapsed": int(states[1]), "done": int(states[3])},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "evolve_kernel<P=%d,W=%d> (%d instances)" % (classes[k]["P"], classes[k]["W"],
+                                                                          classes[k]["members"]),
+                     "launch_ms": ms, "flop_per_pt_stage": FLOP_PER_PT_STAGE},
+        "effective_hbm_GBs": value * BYTES_PER_PT_STEP / 1e9,
+        "launches": classes,
+    }
+    if not args.no_single:
+        rates = single_instance_rates(adscl, 4096)
+        N = np.asarray(cfg["N"])
+        per = np.asarray(cfg["N"], np.float64) * st["steps"]
+        t_single = sum(float(per[N == n].sum()) / rates[n] for n in rates)
+        out["single_instance"] = {"rates": {str(n): r for n, r in rates.items()},
+                                  "batched_over_single": value / (work / args.steps / t_single)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -53,9 +53,11 @@ enum {
  * delta(0,t) = 0 (proper time at the origin). */
 enum { ADSCL_GAUGE_BOUNDARY = 0, ADSCL_GAUGE_ORIGIN = 1 };
 enum { ADSCL_MEM_HOST = 0, ADSCL_MEM_DEVICE = 1 };
-/* Flags: hold A = 1 and delta = 0 instead of solving the constraints (the
- * fixed-metric case of Sec. IV.C, Table II). */
-enum { ADSCL_FROZEN_METRIC = 1 };
+/* Flags.  ADSCL_FROZEN_METRIC: hold A = 1 and delta = 0 instead of solving the
+ * constraints (the fixed-metric case of Sec. IV.C, Table II).
+ * ADSCL_TIME_KERNELS: bracket every launch of the fused evolution kernel with
+ * HIP events on the stream it runs on (see adscl_kernel_stats). */
+enum { ADSCL_FROZEN_METRIC = 1, ADSCL_TIME_KERNELS = 2 };
 /* Per-instance states.  COLLAPSED: min_i A_i < a_collapse at the start of a step
  * (Sec. II, collapse when min A becomes small); NONFINITE: a non-finite Phi, Pi,
  * A or delta at the start of a step; DONE: reached the requested end time. */
@@ -132,6 +134,17 @@ int adscl_spectrum(adscl_ctx* ctx, int32_t J, double* E, double* Pihat, double* 
 
 /* Block until all work enqueued on the context's stream is done. */
 int adscl_sync(adscl_ctx* ctx);
+
+/* Launch plan of the fused evolution kernel.  Instances are grouped into
+ * classes that share a kernel configuration (P grid points per lane, W
+ * wavefronts per instance); each class is one launch on its own stream.
+ * Host outputs (any may be NULL): n_classes; per class (up to max_classes):
+ * P, W, number of member instances, and the duration in ms of its launch in
+ * the last adscl_step call (measured with HIP events on the class's stream when
+ * the context was created with ADSCL_TIME_KERNELS, else -1); cls [n_inst]: the
+ * class of each instance.  Synchronises the context's stream. */
+int adscl_kernel_stats(adscl_ctx* ctx, int32_t max_classes, int32_t* n_classes, int32_t* P, int32_t* W,
+                       int32_t* members, double* last_ms, int32_t* cls);
 
 /* Packed offsets off_b (host [n_inst]) and the total sum N_b. */
 int adscl_layout(const adscl_ctx* ctx, int64_t* off, int64_t* total);

@@ -17,12 +17,13 @@ OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GAUGE_BOUNDARY, GAUGE_ORIGIN = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 FROZEN_METRIC = 1
+TIME_KERNELS = 2
 RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
 
 # Every function include/adscl.h declares.
 EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
            "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum",
-           "adscl_sync", "adscl_layout", "adscl_last_error")
+           "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error")
 
 
 class AdsclError(RuntimeError):
@@ -65,6 +66,7 @@ def lib():
         "adscl_spectrum": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_int]),
         "adscl_sync": (ctypes.c_int, [_vp]),
         "adscl_layout": (ctypes.c_int, [_vp, _vp, _vp]),
+        "adscl_kernel_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
         "adscl_last_error": (ctypes.c_char_p, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -200,6 +202,19 @@ class Batch:
         E, P, F = (np.zeros((self.n_inst, J)) for _ in range(3))
         self._check(lib().adscl_spectrum(self._h, int(J), E.ctypes.data, P.ctypes.data, F.ctypes.data, MEM_HOST))
         return E, P, F
+
+    def kernel_stats(self):
+        """Launch classes: list of dicts (P, W, members, last_ms) and the class
+        index of every instance."""
+        n = ctypes.c_int32(0)
+        self._check(lib().adscl_kernel_stats(self._h, 0, ctypes.addressof(n), None, None, None, None, None))
+        k = n.value
+        P, W, M = (np.zeros(k, np.int32) for _ in range(3))
+        ms = np.zeros(k)
+        cls = np.zeros(self.n_inst, np.int32)
+        self._check(lib().adscl_kernel_stats(self._h, k, ctypes.addressof(n), P.ctypes.data, W.ctypes.data,
+                                             M.ctypes.data, ms.ctypes.data, cls.ctypes.data))
+        return [dict(P=int(P[i]), W=int(W[i]), members=int(M[i]), last_ms=float(ms[i])) for i in range(k)], cls
 
     def split(self, packed):
         """List of per-instance views of a packed array."""

@@ -30,6 +30,8 @@ struct LaunchClass {
     int32_t* d_order = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // timing (ADSCL_TIME_KERNELS)
+    bool timed = false;
 };
 
 // Host-side tables of one grid size N.
@@ -107,7 +109,7 @@ ClassCfg choose_class(int N)
             pos = end + 1;
         }
     }
-    static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {16, 4}};
+    static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 8}};
     for (const ClassCfg& c : pref)
         if (64 * c.W * c.P >= N - 1) return c;
     return ClassCfg{0, 0};
@@ -231,29 +233,23 @@ int upload_ic(adscl_ctx* c, double t_end)
     return ADSCL_OK;
 }
 
-// Run the fused kernel over all classes concurrently (one stream per class,
-// joined back into the context stream).
-int run_evolve(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every, int32_t n_slots, double* snaps)
+// One segment of the fused kernel over all classes concurrently (one stream
+// per class, joined back into the context stream): every instance advances to
+// its target step, or to its next multiple of snap_every when that is > 0.
+int run_evolve(adscl_ctx* c, int32_t snap_every)
 {
-    int rc = upload_ic(c, t_end);
-    if (rc) return rc;
     EvolveArgs a;
     a.Phi = c->state5;
     a.Pi = c->state5 + c->total;
-    a.A = c->state5 + 2 * c->total;
-    a.delta = c->state5 + 3 * c->total;
-    a.m = c->state5 + 4 * c->total;
     a.ic = c->d_ic;
     a.tab = c->d_tab;
     a.status = c->d_status;
-    a.snaps = snaps;
     a.total = c->total;
-    a.max_steps = max_steps;
     a.a_collapse = c->thr;
     a.snap_every = snap_every;
-    a.n_slots = n_slots;
     a.gauge = c->gauge;
     a.frozen = (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0;
+    a.pad = 0;
     hipEvent_t fork;
     HIP_TRY(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     HIP_TRY(c, hipEventRecord(fork, c->stream));
@@ -261,7 +257,12 @@ int run_evolve(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every
         hipStream_t s = c->classes.size() == 1 ? c->stream : lc.stream;
         if (s != c->stream) HIP_TRY(c, hipStreamWaitEvent(s, fork, 0));
         a.order = lc.d_order;
+        if (lc.t0) HIP_TRY(c, hipEventRecord(lc.t0, s));
         HIP_TRY(c, launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s));
+        if (lc.t1) {
+            HIP_TRY(c, hipEventRecord(lc.t1, s));
+            lc.timed = true;
+        }
         if (s != c->stream) {
             HIP_TRY(c, hipEventRecord(lc.done, s));
             HIP_TRY(c, hipStreamWaitEvent(c->stream, lc.done, 0));
@@ -271,15 +272,51 @@ int run_evolve(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every
     return ADSCL_OK;
 }
 
+int run_finalize(adscl_ctx* c, bool final, int32_t snap_every, int32_t n_slots, double* snaps)
+{
+    HIP_TRY(c, launch_finalize(c->n_inst, c->d_ic, c->d_status, c->state5, c->total, c->gauge,
+                               (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0, c->thr, final, snap_every, n_slots,
+                               snaps, c->stream));
+    return ADSCL_OK;
+}
+
+// Whole call: targets, then either one segment, or segments between snapshot
+// steps with a snapshot after each; then the final solve and status.
+int run_call(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every, int32_t n_slots, double* snaps)
+{
+    int rc = upload_ic(c, t_end);
+    if (rc) return rc;
+    HIP_TRY(c, launch_set_targets(c->n_inst, c->d_ic, c->d_status, max_steps, c->stream));
+    if (snap_every > 0 && n_slots > 0) {
+        if ((rc = run_finalize(c, false, snap_every, n_slots, snaps))) return rc;
+        std::vector<InstStatus> st(c->n_inst);
+        for (;;) {
+            HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_status, sizeof(InstStatus) * c->n_inst,
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            bool more = false;
+            for (const InstStatus& s : st)
+                if ((s.state == ST_RUNNING || s.state == ST_DONE) && s.steps < s.target) more = true;
+            if (!more) break;
+            if ((rc = run_evolve(c, snap_every))) return rc;
+            if ((rc = run_finalize(c, false, snap_every, n_slots, snaps))) return rc;
+        }
+    } else {
+        if ((rc = run_evolve(c, 0))) return rc;
+    }
+    return run_finalize(c, true, 0, 0, nullptr);
+}
+
 int after_init(adscl_ctx* c)
 {
     double* Phi = c->state5;
     double* Pi = c->state5 + c->total;
     HIP_TRY(c, launch_pins(c->n_inst, c->d_ic, Phi, Pi, c->stream));
     HIP_TRY(c, launch_reset_status(c->n_inst, c->d_status, c->stream));
-    // solve the constraints at t = 0 (no step), flag collapsed / non-finite data
-    int rc = run_evolve(c, 0, 1.0e300, 0, 0, nullptr);
+    int rc = upload_ic(c, 1.0e300);
     if (rc) return rc;
+    // solve the constraints at t = 0 (no step), flag collapsed / non-finite data
+    if ((rc = run_finalize(c, true, 0, 0, nullptr))) return rc;
     c->initialized = true;
     return ADSCL_OK;
 }
@@ -306,7 +343,7 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     if (!(cfg->a_collapse >= 0.0 && cfg->a_collapse <= 1.0)) return fail(nullptr, ADSCL_EINVAL, "a_collapse must be in [0, 1]");
     if (cfg->gauge != ADSCL_GAUGE_BOUNDARY && cfg->gauge != ADSCL_GAUGE_ORIGIN) return fail(nullptr, ADSCL_EINVAL, "bad gauge");
     if (cfg->n_modes < 0 || cfg->n_modes > 128) return fail(nullptr, ADSCL_EINVAL, "n_modes must be in [0, 128]");
-    if (cfg->flags & ~ADSCL_FROZEN_METRIC) return fail(nullptr, ADSCL_EINVAL, "unknown flags");
+    if (cfg->flags & ~(ADSCL_FROZEN_METRIC | ADSCL_TIME_KERNELS)) return fail(nullptr, ADSCL_EINVAL, "unknown flags");
 
     adscl_ctx* c = new adscl_ctx();
     c->n_inst = cfg->n_inst;
@@ -420,6 +457,10 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
             TRY_C(hipStreamCreateWithFlags(&lc.stream, hipStreamNonBlocking));
             TRY_C(hipEventCreateWithFlags(&lc.done, hipEventDisableTiming));
         }
+        if (c->flags & ADSCL_TIME_KERNELS) {
+            TRY_C(hipEventCreate(&lc.t0));
+            TRY_C(hipEventCreate(&lc.t1));
+        }
     }
     // launch the biggest classes first
     std::stable_sort(c->classes.begin(), c->classes.end(), [](const LaunchClass& x, const LaunchClass& y) {
@@ -465,6 +506,8 @@ void adscl_destroy(adscl_ctx* c)
         if (lc.d_order) hipFree(lc.d_order);
         if (lc.stream) hipStreamDestroy(lc.stream);
         if (lc.done) hipEventDestroy(lc.done);
+        if (lc.t0) hipEventDestroy(lc.t0);
+        if (lc.t1) hipEventDestroy(lc.t1);
     }
     for (auto& kv : c->tables) {
         if (kv.second.d_tab) hipFree(kv.second.d_tab);
@@ -545,7 +588,7 @@ int adscl_step(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every
             HIP_TRY(c, hipMemcpy(dsn, snaps, snap_bytes, hipMemcpyHostToDevice));
         }
     }
-    int rc = run_evolve(c, max_steps, t_end, want ? snap_every : 0, want ? n_snap_slots : 0, dsn);
+    int rc = run_call(c, max_steps, t_end, want ? snap_every : 0, want ? n_snap_slots : 0, dsn);
     if (want && mem == ADSCL_MEM_HOST) {
         if (rc == ADSCL_OK) {
             hipError_t e = hipMemcpyAsync(snaps, dsn, snap_bytes, hipMemcpyDeviceToHost, c->stream);
@@ -639,6 +682,30 @@ int adscl_sync(adscl_ctx* c)
 {
     if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return ADSCL_OK;
+}
+
+int adscl_kernel_stats(adscl_ctx* c, int32_t max_classes, int32_t* n_classes, int32_t* P, int32_t* W,
+                       int32_t* members, double* last_ms, int32_t* cls)
+{
+    if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
+    if (max_classes < 0) return fail(c, ADSCL_EINVAL, "max_classes < 0");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int nc = (int)c->classes.size();
+    if (n_classes) *n_classes = nc;
+    for (int k = 0; k < nc && k < max_classes; ++k) {
+        LaunchClass& lc = c->classes[k];
+        if (P) P[k] = lc.cfg.P;
+        if (W) W[k] = lc.cfg.W;
+        if (members) members[k] = (int32_t)lc.inst.size();
+        if (last_ms) {
+            float ms = -1.0f;
+            if (lc.t0 && lc.timed) HIP_TRY(c, hipEventElapsedTime(&ms, lc.t0, lc.t1));
+            last_ms[k] = ms;
+        }
+        if (cls)
+            for (int32_t b : lc.inst) cls[b] = k;
+    }
     return ADSCL_OK;
 }
 

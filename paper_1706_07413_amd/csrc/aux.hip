@@ -59,12 +59,227 @@ __global__ void reset_status_kernel(int n_inst, InstStatus* st)
     if (b >= n_inst) return;
     InstStatus o;
     o.steps = 0;
+    o.target = 0;
     o.t_c = -1.0;
     o.minA = 1.0;
     o.mass = 0.0;
     o.state = ST_RUNNING;
     o.pad = 0;
     st[b] = o;
+}
+
+__global__ void set_targets_kernel(int n_inst, const InstConst* ic, InstStatus* st, int64_t max_steps)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_inst) return;
+    InstStatus o = st[b];
+    int64_t t = o.steps + max_steps;
+    if (t > ic[b].n_final) t = ic[b].n_final;
+    if (t < o.steps) t = o.steps;
+    o.target = t;
+    st[b] = o;
+}
+
+// Block-wide exclusive prefix sum of one value per thread (256 threads).
+__device__ double block_excl_scan(double v, double* sh, double& total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_up(x, d, 64);
+        if (lane >= d) x += t;
+    }
+    __syncthreads();
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    double carry = 0.0;
+    total = 0.0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wv) carry += sh[w];
+        total += sh[w];
+    }
+    return carry + x - v;
+}
+
+struct FinArgs {
+    const InstConst* ic;
+    InstStatus* st;
+    double* state5;
+    int64_t total;
+    double a_collapse;
+    double* snaps;
+    int32_t snap_every;
+    int32_t n_slots;
+    int32_t gauge;
+    int32_t frozen;
+    int32_t final_;
+    int32_t pad;
+};
+
+// Constraint solve of the packed state of one instance per 256-thread block
+// (Sec. II, Eqs. (5)-(6), the same discretisation as the evolution kernel:
+// 4-point cell rule in prefix-sum form, m = (1 - A) sin x / cos^3 x), written
+// out as (Phi, Pi, A, delta, m); then min A, the mass m(pi/2) and, at the end
+// of a call, the collapse / non-finite test of the final state.
+__global__ void __launch_bounds__(256) finalize_kernel(FinArgs f)
+{
+    __shared__ double sh[16];
+    __shared__ int ish[4];
+    const int b = blockIdx.x;
+    const InstStatus st = f.st[b];
+    const InstConst c = f.ic[b];
+    const bool snap = f.snaps && f.snap_every > 0 && (st.steps % f.snap_every) == 0 &&
+                      (st.steps / f.snap_every) < f.n_slots;
+    if (!snap && !f.final_) return;
+    const int N = c.N;
+    const double h = c.h;
+    const double* Phi = f.state5 + c.off;
+    const double* Pi = f.state5 + f.total + c.off;
+    double* dst[2] = {f.final_ ? f.state5 : nullptr,
+                      snap ? f.snaps + (size_t)(st.steps / f.snap_every) * 5 * (size_t)f.total : nullptr};
+    // scratch for delta~ before the gauge shift: the delta row of the first target
+    double* dscr = (dst[0] ? dst[0] : dst[1]) + 3 * f.total + c.off;
+
+    const int tid = threadIdx.x;
+    const int C = (N + 255) / 256;
+    const int i0 = tid * C;
+    const int i1 = min(N, i0 + C);
+    auto q_at = [&](int i) -> double { return Phi[i] * Phi[i] + Pi[i] * Pi[i]; };
+    auto sc_at = [&](int i) -> double {
+        const double x = (double)i * h;
+        return sin(x) * cos(x);
+    };
+    auto t2_at = [&](int i) -> double {
+        const double t = tan((double)i * h);
+        return t * t;
+    };
+    // p = sin x cos x q: 0 at both ends, odd ghosts about both ends
+    auto p_at = [&](int i) -> double {
+        double sgn = 1.0;
+        if (i < 0) { i = -i; sgn = -1.0; }
+        if (i > N - 1) { i = 2 * (N - 1) - i; sgn = -sgn; }
+        if (i == 0 || i == N - 1) return 0.0;
+        return sgn * sc_at(i) * q_at(i);
+    };
+
+    double dN = 0.0, tot2 = 0.0, shift = 0.0;
+    if (!f.frozen) {
+        double ps = 0.0;
+        for (int i = i0; i < i1; ++i) ps += p_at(i);
+        double tot;
+        const double carry = block_excl_scan(ps, sh, tot);
+        const double p1 = p_at(1);
+        double R = carry;
+        for (int i = i0; i < i1; ++i) {
+            const double pi_ = p_at(i);
+            R += pi_;
+            dscr[i] = -(h / 24.0) * (24.0 * R - 12.0 * pi_ + p_at(i - 1) - p_at(i + 1) + 2.0 * p1);
+        }
+        dN = -(h / 24.0) * (24.0 * tot + 2.0 * p_at(N - 2) + 2.0 * p1);
+        shift = (f.gauge == 0) ? dN : 0.0;
+        __syncthreads();
+    }
+    // sigma = tan^2 x q e^{-delta}: 0 at both ends, even ghosts
+    auto sig_at = [&](int i) -> double {
+        if (i < 0) i = -i;
+        if (i > N - 1) i = 2 * (N - 1) - i;
+        if (i == 0 || i == N - 1) return 0.0;
+        return t2_at(i) * q_at(i) * exp(-(dscr[i] - shift));
+    };
+    double mn = 1.0, chk = 0.0;
+    int col = 0;
+    if (!f.frozen) {
+        double ss = 0.0;
+        for (int i = i0; i < i1; ++i) ss += sig_at(i);
+        double carry2 = block_excl_scan(ss, sh + 4, tot2);
+        double R2 = carry2;
+        for (int i = i0; i < i1; ++i) {
+            const double si = sig_at(i);
+            R2 += si;
+            const double S = (h / 24.0) * (24.0 * R2 - 12.0 * si + sig_at(i - 1) - sig_at(i + 1));
+            const double dl = dscr[i] - shift;
+            const double E = exp(-dl);
+            const double m = S / E;
+            double A = 1.0;
+            if (i >= 1 && i <= N - 2) {
+                const double x = (double)i * h;
+                const double s = sin(x), co = cos(x);
+                const double c3s = co * co * co / s;
+                A = 1.0 - c3s * m;
+                if (E - c3s * S < f.a_collapse * E) col = 1;
+            }
+            mn = fmin(mn, A);
+            chk = fma(q_at(i), 0.0, chk);
+            chk = fma(A, 0.0, chk);
+            chk = fma(dl, 0.0, chk);
+            for (int d = 0; d < 2; ++d) {
+                if (!dst[d]) continue;
+                dst[d][2 * f.total + c.off + i] = A;
+                dst[d][4 * f.total + c.off + i] = m;
+            }
+        }
+        __syncthreads();  // all reads of the delta~ scratch are done
+        for (int i = i0; i < i1; ++i) {
+            const double dl = (i == N - 1) ? ((f.gauge == 0) ? 0.0 : dN) : dscr[i] - shift;
+            for (int d = 0; d < 2; ++d)
+                if (dst[d]) dst[d][3 * f.total + c.off + i] = dl;
+        }
+    } else {
+        for (int i = i0; i < i1; ++i) {
+            chk = fma(q_at(i), 0.0, chk);
+            for (int d = 0; d < 2; ++d) {
+                if (!dst[d]) continue;
+                double* o = dst[d];
+                o[2 * f.total + c.off + i] = 1.0;
+                o[3 * f.total + c.off + i] = 0.0;
+                o[4 * f.total + c.off + i] = 0.0;
+            }
+        }
+    }
+    if (dst[1]) {
+        double* o = dst[1];
+        for (int i = i0; i < i1; ++i) {
+            o[c.off + i] = Phi[i];
+            o[f.total + c.off + i] = Pi[i];
+        }
+    }
+    if (!isfinite(chk) || !isfinite(dN)) col |= 2;
+    if (1.0 < f.a_collapse) col |= 1;
+    // block reductions of min A and the flags
+    for (int d = 32; d >= 1; d >>= 1) mn = fmin(mn, __shfl_xor(mn, d, 64));
+    const int wcol = __any(col & 1) ? 1 : 0;
+    const int wnf = __any(col & 2) ? 2 : 0;
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        sh[8 + (tid >> 6)] = mn;
+        ish[tid >> 6] = wcol | wnf;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double mA = 1.0;
+        int fl = 0;
+        for (int w = 0; w < 4; ++w) {
+            mA = fmin(mA, sh[8 + w]);
+            fl |= ish[w];
+        }
+        if (f.final_) {
+            InstStatus o = st;
+            o.minA = mA;
+            o.mass = f.frozen ? 0.0 : h * tot2 / ((f.gauge == 0) ? 1.0 : exp(-dN));
+            if (o.state == ST_RUNNING || o.state == ST_DONE) {
+                if (fl & 2) {
+                    o.state = ST_NONFINITE;
+                    o.t_c = (double)o.steps * c.dt;
+                } else if (fl & 1) {
+                    o.state = ST_COLLAPSED;
+                    o.t_c = (double)o.steps * c.dt;
+                } else {
+                    o.state = (o.steps >= c.n_final) ? ST_DONE : ST_RUNNING;
+                }
+            }
+            f.st[b] = o;
+        }
+    }
 }
 
 __device__ double block_reduce(double v, bool take_max, double* sh)
@@ -170,6 +385,33 @@ hipError_t launch_pins(int n_inst, const InstConst* ic, double* Phi, double* Pi,
 hipError_t launch_reset_status(int n_inst, InstStatus* st, hipStream_t s)
 {
     reset_status_kernel<<<dim3((n_inst + 255) / 256), dim3(256), 0, s>>>(n_inst, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_targets(int n_inst, const InstConst* ic, InstStatus* st, int64_t max_steps, hipStream_t s)
+{
+    set_targets_kernel<<<dim3((n_inst + 255) / 256), dim3(256), 0, s>>>(n_inst, ic, st, max_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, double* state5, int64_t total,
+                           int gauge, int frozen, double a_collapse, bool final, int32_t snap_every,
+                           int32_t n_slots, double* snaps, hipStream_t s)
+{
+    FinArgs f;
+    f.ic = ic;
+    f.st = st;
+    f.state5 = state5;
+    f.total = total;
+    f.a_collapse = a_collapse;
+    f.snaps = snaps;
+    f.snap_every = snap_every;
+    f.n_slots = n_slots;
+    f.gauge = gauge;
+    f.frozen = frozen;
+    f.final_ = final ? 1 : 0;
+    f.pad = 0;
+    finalize_kernel<<<dim3(n_inst), dim3(256), 0, s>>>(f);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ enum : int32_t { ST_RUNNING = 0, ST_COLLAPSED = 1, ST_NONFINITE = 2, ST_DONE = 3
 // Per-instance status kept on the device.
 struct InstStatus {
     int64_t steps;   // current step n (state is U^n)
+    int64_t target;  // last step of the current call
     double t_c;      // time of collapse / non-finite detection, -1 if none
     double minA;     // min A of U^n
     double mass;     // m(pi/2) of U^n
@@ -45,14 +46,12 @@ struct EvolveArgs {
     const int32_t* order;   // instance index per workgroup of this launch
     const double* const* tab;  // per instance: lane-interleaved tables of its class
     InstStatus* status;     // [n_inst]
-    double* snaps;          // [n_slots][5][total] or null
     int64_t total;
-    int64_t max_steps;
     double a_collapse;
-    int32_t snap_every;
-    int32_t n_slots;
+    int32_t snap_every;     // > 0: stop each instance at the next multiple
     int32_t gauge;          // 0 boundary, 1 origin
     int32_t frozen;
+    int32_t pad;
 };
 
 // A kernel configuration: P grid points per lane, W wavefronts per instance.
@@ -81,6 +80,16 @@ hipError_t launch_init_modes(int n_inst, const InstConst* ic, const double* eps,
 // Pins Phi_0 = Phi_{N-1} = Pi_{N-1} = 0.
 hipError_t launch_pins(int n_inst, const InstConst* ic, double* Phi, double* Pi, hipStream_t s);
 hipError_t launch_reset_status(int n_inst, InstStatus* st, hipStream_t s);
+// target = clamp(steps + max_steps, steps, n_final) for instances still evolving.
+hipError_t launch_set_targets(int n_inst, const InstConst* ic, InstStatus* st, int64_t max_steps, hipStream_t s);
+// Constraint solve of the packed state (Phi, Pi) -> A, delta, m, min A, mass.
+// Writes (Phi, Pi, A, delta, m) to `out` (5 rows of `total`) when `final` and
+// to snapshot slot steps / snap_every when snapshots are on and due; when
+// `final`, an instance at its target is tested for collapse / non-finite data
+// and marked DONE at n_final.
+hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, double* state5, int64_t total,
+                           int gauge, int frozen, double a_collapse, bool final, int32_t snap_every,
+                           int32_t n_slots, double* snaps, hipStream_t s);
 // Diagnostics: out[b*4 + {0..3}] = max|R_A'|, max|R_delta'|, m(pi/2), M (cell rule).
 hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi, const double* Pi,
                               const double* A, const double* delta, const double* m, double* out,
