@@ -52,6 +52,12 @@ def _load():
         "ora_spectrum": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
         "ora_init_gaussian": (None, [_i, _d, _d, _p, _p]),
         "ora_init_modes": (None, [_i, _d, _i, _p, _p, _p]),
+        "ora_objective": (_i, [_i, _i, _d, _d, _d, _d, _i, _p, _i, _i64, _i64, _p, _p, _p, _p]),
+        "ora_constraints_vjp": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
+        "ora_rhs_vjp": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+        "ora_step": (None, [_i, _i, _d, _d, _p, _p]),
+        "ora_step_vjp": (None, [_i, _i, _d, _d, _p, _p, _p, _p]),
+        "ora_spectrum_vjp": (None, [_i, _i, _p, _p, _p, _p, _p, _p, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -209,3 +215,68 @@ def init_modes(N, eps, c):
     Phi, Pi = np.empty(N), np.empty(N)
     lib.ora_init_modes(N, eps, len(c), _ptr(c), _ptr(Phi), _ptr(Pi))
     return Phi, Pi
+
+
+# ---------------------------------------------------------------------------
+# Reverse-mode derivative (adscl_oracle_adj.c)
+# ---------------------------------------------------------------------------
+
+def objective(N, eps, c, T=None, n_steps=None, J=16, K=512, gauge=GAUGE_BOUNDARY, cfl=0.25, ko=0.5,
+              a_collapse=0.0, grad=True):
+    """L = sum_{j<J} (E_j(t_n) - E_j(0))^2 for Pi(x,0) = eps sum_k c_k e_k(x),
+    Phi(x,0) = 0, and dL/dc by the discrete adjoint with checkpoints every K
+    steps.  Returns dict L, grad (None if not asked or invalid), valid, E0, ET."""
+    lib = _load()
+    c = _f64(c)
+    if n_steps is None:
+        n_steps = n_steps_for(T, N, cfl)
+    Lv = _d(0)
+    g = np.zeros(len(c))
+    E0, ET = np.zeros(J), np.zeros(J)
+    valid = lib.ora_objective(N, gauge, cfl, ko, a_collapse, eps, len(c), _ptr(c), J, int(n_steps), int(K),
+                              ctypes.byref(Lv), _ptr(g) if grad else None, _ptr(E0), _ptr(ET))
+    return dict(L=Lv.value, grad=(g if (grad and valid) else None), valid=bool(valid), E0=E0, ET=ET,
+                n_steps=int(n_steps))
+
+
+def constraints_vjp(Phi, Pi, Abar, dbar, gauge=GAUGE_BOUNDARY):
+    lib = _load()
+    Phi, Pi, Abar, dbar = map(_f64, (Phi, Pi, Abar, dbar))
+    N = len(Phi)
+    Pb, Qb = np.zeros(N), np.zeros(N)
+    lib.ora_constraints_vjp(N, gauge, _ptr(Phi), _ptr(Pi), _ptr(Abar), _ptr(dbar), _ptr(Pb), _ptr(Qb))
+    return Pb, Qb
+
+
+def rhs_vjp(Phi, Pi, A, delta, kbar0, kbar1, ko=0.5, frozen=False):
+    lib = _load()
+    Phi, Pi, A, delta, kbar0, kbar1 = map(_f64, (Phi, Pi, A, delta, kbar0, kbar1))
+    N = len(Phi)
+    out = [np.zeros(N) for _ in range(4)]
+    lib.ora_rhs_vjp(N, ko, int(frozen), _ptr(Phi), _ptr(Pi), _ptr(A), _ptr(delta), _ptr(kbar0), _ptr(kbar1),
+                    *[_ptr(o) for o in out])
+    return out
+
+
+def step(Phi, Pi, gauge=GAUGE_BOUNDARY, cfl=0.25, ko=0.5):
+    lib = _load()
+    Phi, Pi = _f64(Phi).copy(), _f64(Pi).copy()
+    lib.ora_step(len(Phi), gauge, cfl, ko, _ptr(Phi), _ptr(Pi))
+    return Phi, Pi
+
+
+def step_vjp(Phi, Pi, Phibar, Pibar, gauge=GAUGE_BOUNDARY, cfl=0.25, ko=0.5):
+    lib = _load()
+    Phi, Pi = _f64(Phi), _f64(Pi)
+    Pb, Qb = _f64(Phibar).copy(), _f64(Pibar).copy()
+    lib.ora_step_vjp(len(Phi), gauge, cfl, ko, _ptr(Phi), _ptr(Pi), _ptr(Pb), _ptr(Qb))
+    return Pb, Qb
+
+
+def spectrum_vjp(Phi, Pi, A, Ebar):
+    lib = _load()
+    Phi, Pi, A, Ebar = map(_f64, (Phi, Pi, A, Ebar))
+    N = len(Phi)
+    out = [np.zeros(N) for _ in range(3)]
+    lib.ora_spectrum_vjp(N, len(Ebar), _ptr(Phi), _ptr(Pi), _ptr(A), _ptr(Ebar), *[_ptr(o) for o in out])
+    return out

@@ -37,32 +37,19 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORA_PI 3.14159265358979323846
-
-enum { ORA_GAUGE_BOUNDARY = 0, ORA_GAUGE_ORIGIN = 1 };
-enum { ORA_RUNNING = 0, ORA_COLLAPSED = 1, ORA_NONFINITE = 2, ORA_DONE = 3 };
+#include "oracle_internal.h"
 
 /* ------------------------------------------------------------------------ */
 /* Grid and coefficient tables                                               */
 /* ------------------------------------------------------------------------ */
 
-typedef struct {
-    int N;
-    double h;
-    double *x, *sn, *cs;   /* sin x_i, cos x_i (exact 0/1 at the two ends)      */
-    double *sc;            /* sin x cos x                                        */
-    double *t2;            /* tan^2 x (0 at x=0; unused at x=pi/2)               */
-    double *ct2;           /* 1/tan^2 x (interior only)                          */
-    double *c3s;           /* cos^3 x / sin x (interior only)                    */
-} ora_grid;
-
-static void grid_free(ora_grid* g)
+void grid_free(ora_grid* g)
 {
     free(g->x); free(g->sn); free(g->cs); free(g->sc);
     free(g->t2); free(g->ct2); free(g->c3s);
 }
 
-static void grid_make(ora_grid* g, int N)
+void grid_make(ora_grid* g, int N)
 {
     int i;
     g->N = N;
@@ -109,7 +96,7 @@ void ora_tables(int N, double* x, double* sc, double* t2, double* ct2, double* c
  * p0/p1 are +1 (even) or -1 (odd) about x=0 / x=pi/2.  Smooth solutions of the
  * regular problem are even/odd functions about both ends (regularity at the
  * origin, Eqs. (7)-(8); reflecting boundary, Eqs. (9)-(11)). */
-static double gv(const double* u, int N, int i, double p0, double p1)
+double gv(const double* u, int N, int i, double p0, double p1)
 {
     if (i < 0) return p0 * u[-i];
     if (i > N - 1) return p1 * u[2 * (N - 1) - i];
@@ -117,14 +104,14 @@ static double gv(const double* u, int N, int i, double p0, double p1)
 }
 
 /* 4th-order centred first derivative at i. */
-static double stencil_D(const double* u, int N, int i, double h, double p0, double p1)
+double stencil_D(const double* u, int N, int i, double h, double p0, double p1)
 {
     return (gv(u, N, i - 2, p0, p1) - 8.0 * gv(u, N, i - 1, p0, p1)
             + 8.0 * gv(u, N, i + 1, p0, p1) - gv(u, N, i + 2, p0, p1)) / (12.0 * h);
 }
 
 /* Kreiss-Oliger dissipation built on the 6th undivided difference. */
-static double stencil_KO(const double* u, int N, int i, double h, double sig, double p0, double p1)
+double stencil_KO(const double* u, int N, int i, double h, double sig, double p0, double p1)
 {
     double d6 = gv(u, N, i - 3, p0, p1) - 6.0 * gv(u, N, i - 2, p0, p1)
               + 15.0 * gv(u, N, i - 1, p0, p1) - 20.0 * u[i]
@@ -135,7 +122,7 @@ static double stencil_KO(const double* u, int N, int i, double h, double sig, do
 
 /* Integral of u over the cell [x_i, x_{i+1}] by the 4-point rule that is exact
  * for cubics through x_{i-1}..x_{i+2}. */
-static double cell4(const double* u, int N, int i, double h, double p0, double p1)
+double cell4(const double* u, int N, int i, double h, double p0, double p1)
 {
     return h * (-gv(u, N, i - 1, p0, p1) + 13.0 * u[i] + 13.0 * gv(u, N, i + 1, p0, p1)
                 - gv(u, N, i + 2, p0, p1)) / 24.0;
@@ -163,11 +150,7 @@ void ora_op_cell4(int N, double h, const double* u, int p0, int p1, double* out)
 /* Constraint solve, Sec. II Eqs. (5)-(6) with the gauge choice Eq. (12)     */
 /* ------------------------------------------------------------------------ */
 
-typedef struct {
-    double *q, *p, *dtil, *E, *sig, *S;
-} ora_cwork;
-
-static void cwork_alloc(ora_cwork* w, int N)
+void cwork_alloc(ora_cwork* w, int N)
 {
     w->q = malloc(sizeof(double) * N);
     w->p = malloc(sizeof(double) * N);
@@ -177,7 +160,7 @@ static void cwork_alloc(ora_cwork* w, int N)
     w->S = malloc(sizeof(double) * N);
 }
 
-static void cwork_free(ora_cwork* w)
+void cwork_free(ora_cwork* w)
 {
     free(w->q); free(w->p); free(w->dtil); free(w->E); free(w->sig); free(w->S);
 }
@@ -195,7 +178,7 @@ static void cwork_free(ora_cwork* w)
  * Gauge: boundary time delta(pi/2)=0 (Eq. (12)) shifts delta~ by its last value;
  * the origin gauge keeps delta = delta~ (delta(0)=0).
  */
-static void constraint_solve(const ora_grid* g, int gauge, const double* Phi, const double* Pi,
+void constraint_solve(const ora_grid* g, int gauge, const double* Phi, const double* Pi,
                              ora_cwork* w, double* A, double* delta, double* m)
 {
     int N = g->N, i;
@@ -241,11 +224,7 @@ void ora_constraints(int N, int gauge, const double* Phi, const double* Pi,
 /* Right-hand sides, Sec. II Eqs. (2)-(3)                                    */
 /* ------------------------------------------------------------------------ */
 
-typedef struct {
-    double *w, *f1, *f2, *g;
-} ora_rwork;
-
-static void rwork_alloc(ora_rwork* r, int N)
+void rwork_alloc(ora_rwork* r, int N)
 {
     r->w = malloc(sizeof(double) * N);
     r->f1 = malloc(sizeof(double) * N);
@@ -253,7 +232,7 @@ static void rwork_alloc(ora_rwork* r, int N)
     r->g = malloc(sizeof(double) * N);
 }
 
-static void rwork_free(ora_rwork* r)
+void rwork_free(ora_rwork* r)
 {
     free(r->w); free(r->f1); free(r->f2); free(r->g);
 }
@@ -271,7 +250,7 @@ static void rwork_free(ora_rwork* r)
  * Ghost parities: Phi odd/even, Pi even/odd, f1 even/odd, g and f2 odd/even
  * (first entry about x=0, second about x=pi/2).
  */
-static void rhs_eval(const ora_grid* gr, double ko, int frozen, const double* Phi, const double* Pi,
+void rhs_eval(const ora_grid* gr, double ko, int frozen, const double* Phi, const double* Pi,
                      const double* A, const double* delta, ora_rwork* r, double* dPhi, double* dPi)
 {
     int N = gr->N, i;
@@ -312,7 +291,7 @@ void ora_rhs(int N, double ko, int frozen, const double* Phi, const double* Pi,
 
 /* A and delta of a stage input: the constraint solve, or A=1, delta=0 when the
  * metric is frozen (the fixed-metric case of Table II). */
-static void stage_metric(const ora_grid* g, int gauge, int frozen, const double* Phi, const double* Pi,
+void stage_metric(const ora_grid* g, int gauge, int frozen, const double* Phi, const double* Pi,
                          ora_cwork* w, double* A, double* delta, double* m)
 {
     int i;
