@@ -84,10 +84,10 @@ def single_instance_rates(adscl, steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2, help="timed passes over the batch")
+    ap.add_argument("--steps", type=int, default=1, help="timed passes over the batch")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--t-end", type=float, default=5.0,
-                    help="end time of every pass (the workload's full run is 50)")
+    ap.add_argument("--t-end", type=float, default=50.0,
+                    help="end time of every pass (default: the workload's full run, 50)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
@@ -148,6 +148,11 @@ def main():
     ms = classes[k]["last_ms"]
     achieved = unit_steps * 4 * FLOP_PER_PT_STAGE / (ms * 1e-3) / 1e12
     states = np.bincount(st["state"], minlength=4)
+    per_n = {}
+    for n in (1025, 2049, 4097):
+        sel = np.asarray(cfg["N"]) == n
+        per_n[str(n)] = {"instances": int(sel.sum()), "collapsed": int((st["state"][sel] == 1).sum()),
+                         "pt_steps": pt_steps(np.asarray(cfg["N"])[sel], st["steps"][sel])}
 
     out = {
         "metric": METRIC,
@@ -166,7 +171,7 @@ def main():
                                "eps log-U[1,40], sigma U[1/16,1/4], RK4 dt=h/4, t_end=%g, collapse min A<0.02" % T,
                    "instances": int(len(cfg["N"])), "t_end": T,
                    "pt_steps_per_pass": work / args.steps,
-                   "collapsed": int(states[1]), "done": int(states[3])},
+                   "collapsed": int(states[1]), "done": int(states[3]), "by_N": per_n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel": "evolve_kernel<P=%d,W=%d> (%d instances)" % (classes[k]["P"], classes[k]["W"],

@@ -132,6 +132,29 @@ int adscl_constraints(adscl_ctx* ctx, double* out, int mem);
  * give NaN. */
 int adscl_spectrum(adscl_ctx* ctx, int32_t J, double* E, double* Pihat, double* Phihat, int mem);
 
+/* Gradient of the drift of the low mode energies by the discrete adjoint of the
+ * whole computation (Sec. II: data from a mode spectrum, evolution, normal-mode
+ * decomposition).  For every instance b:
+ *   Pi(x,0) = eps_b sum_{k<Jc} c_{b,k} e_k(x), Phi(x,0) = 0   (as adscl_init_modes),
+ *   evolve n_final_b = ceil(T / dt_b - 1e-9) steps               (as adscl_step),
+ *   L_b = sum_{j<J} (E_j(t_n) - E_j(0))^2, E_j as in adscl_spectrum,
+ * and dL_b/dc_{b,k}: the exact derivative of the discrete computation (initial
+ * map, constraint solves at every RK stage, stencils, RK4 stages, spectrum;
+ * the collapse tests are piecewise constant and contribute nothing).  The state
+ * is stored every ckpt_every steps on the way forward and each segment is
+ * recomputed before it is reversed; device memory per instance is about
+ * 16 N_b (n_final_b / ckpt_every + ckpt_every) bytes plus 150 N_b bytes of
+ * stage scratch, held by the context for reuse.
+ * Inputs: eps [n_inst], c [n_inst x Jc] row-major, 1 <= Jc <= n_modes,
+ * 1 <= J <= n_modes, T >= 0 finite, ckpt_every >= 1.  Outputs: L [n_inst],
+ * dLdc [n_inst x Jc], valid [n_inst] (int32): 1 when the instance reached t_n
+ * with min A >= a_collapse at every step start and at the end; otherwise 0,
+ * dLdc = 0 and L is taken where the evolution stopped.  ADSCL_EUNSUPPORTED for
+ * a context created with ADSCL_FROZEN_METRIC.  Leaves the context in the state
+ * adscl_init_modes followed by adscl_step to T would leave it. */
+int adscl_adjoint(adscl_ctx* ctx, const double* eps, const double* c, int32_t Jc, int32_t J, double T,
+                  int32_t ckpt_every, double* L, double* dLdc, int32_t* valid, int mem);
+
 /* Block until all work enqueued on the context's stream is done. */
 int adscl_sync(adscl_ctx* ctx);
 

@@ -23,7 +23,7 @@ RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
 # Every function include/adscl.h declares.
 EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
            "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum",
-           "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error")
+           "adscl_adjoint", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error")
 
 
 class AdsclError(RuntimeError):
@@ -64,6 +64,7 @@ def lib():
         "adscl_status": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "adscl_constraints": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
         "adscl_spectrum": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_int]),
+        "adscl_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _d, _i32, _vp, _vp, _vp, ctypes.c_int]),
         "adscl_sync": (ctypes.c_int, [_vp]),
         "adscl_layout": (ctypes.c_int, [_vp, _vp, _vp]),
         "adscl_kernel_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -202,6 +203,31 @@ class Batch:
         E, P, F = (np.zeros((self.n_inst, J)) for _ in range(3))
         self._check(lib().adscl_spectrum(self._h, int(J), E.ctypes.data, P.ctypes.data, F.ctypes.data, MEM_HOST))
         return E, P, F
+
+    def adjoint(self, eps, c, J, T, ckpt_every=512):
+        """Drift objective L_b = sum_{j<J} (E_j(T) - E_j(0))^2 of mode-sum data
+        eps_b sum_k c_bk e_k and its gradient dL_b/dc_b (adscl_adjoint).  Host
+        (numpy) or device (torch) inputs; returns (L, dLdc, valid) of the same
+        kind.  Leaves the batch at the final state."""
+        pe, me = _ptr_mem(eps)
+        pc, mc = _ptr_mem(c)
+        assert me == mc
+        n, Jc = self.n_inst, int(c.shape[1])
+        if me == MEM_DEVICE:
+            import torch
+            L = torch.empty(n, dtype=torch.float64, device=c.device)
+            g = torch.empty((n, Jc), dtype=torch.float64, device=c.device)
+            v = torch.empty(n, dtype=torch.int32, device=c.device)
+            pv = v.data_ptr()
+        else:
+            L, g = np.zeros(n), np.zeros((n, Jc))
+            v = np.zeros(n, np.int32)
+            pv = v.ctypes.data
+        self._check(lib().adscl_adjoint(self._h, pe, pc, Jc, int(J), float(T), int(ckpt_every), _ptr_mem(L)[0],
+                                        _ptr_mem(g)[0], pv, me))
+        if me == MEM_DEVICE:
+            self.sync()
+        return L, g, v
 
     def kernel_stats(self):
         """Launch classes: list of dicts (P, W, members, last_ms) and the class

@@ -70,6 +70,8 @@ struct adscl_ctx {
     std::vector<LaunchClass> classes;
     double* d_tmp = nullptr;    // staging for host inputs / outputs
     size_t tmp_bytes = 0;
+    // adjoint working memory, kept for reuse by later calls
+    std::map<std::string, std::pair<void*, size_t>> bufs;
     bool initialized = false;
     std::string err;
 };
@@ -233,36 +235,38 @@ int upload_ic(adscl_ctx* c, double t_end)
     return ADSCL_OK;
 }
 
-// One segment of the fused kernel over all classes concurrently (one stream
-// per class, joined back into the context stream): every instance advances to
-// its target step, or to its next multiple of snap_every when that is > 0.
-int run_evolve(adscl_ctx* c, int32_t snap_every)
+// Device buffer `name` of the context with at least `bytes` bytes (grown, not
+// preserved, when too small).
+int buffer(adscl_ctx* c, const char* name, size_t bytes, void** out)
 {
-    EvolveArgs a;
-    a.Phi = c->state5;
-    a.Pi = c->state5 + c->total;
-    a.ic = c->d_ic;
-    a.tab = c->d_tab;
-    a.status = c->d_status;
-    a.total = c->total;
-    a.a_collapse = c->thr;
-    a.snap_every = snap_every;
-    a.gauge = c->gauge;
-    a.frozen = (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0;
-    a.pad = 0;
+    auto& e = c->bufs[name];
+    if (e.second < bytes) {
+        if (e.first) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipFree(e.first));
+        }
+        e.first = nullptr;
+        e.second = 0;
+        HIP_TRY(c, hipMalloc(&e.first, std::max<size_t>(bytes, 256)));
+        e.second = std::max<size_t>(bytes, 256);
+    }
+    *out = e.first;
+    return ADSCL_OK;
+}
+
+// One launch per class, the classes concurrently (one stream per class, forked
+// from and joined back into the context stream).  `launch(lc, stream)` enqueues
+// the class's work.
+template <class F>
+int run_classes(adscl_ctx* c, F&& launch)
+{
     hipEvent_t fork;
     HIP_TRY(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     HIP_TRY(c, hipEventRecord(fork, c->stream));
     for (LaunchClass& lc : c->classes) {
         hipStream_t s = c->classes.size() == 1 ? c->stream : lc.stream;
         if (s != c->stream) HIP_TRY(c, hipStreamWaitEvent(s, fork, 0));
-        a.order = lc.d_order;
-        if (lc.t0) HIP_TRY(c, hipEventRecord(lc.t0, s));
-        HIP_TRY(c, launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s));
-        if (lc.t1) {
-            HIP_TRY(c, hipEventRecord(lc.t1, s));
-            lc.timed = true;
-        }
+        HIP_TRY(c, launch(lc, s));
         if (s != c->stream) {
             HIP_TRY(c, hipEventRecord(lc.done, s));
             HIP_TRY(c, hipStreamWaitEvent(c->stream, lc.done, 0));
@@ -271,6 +275,51 @@ int run_evolve(adscl_ctx* c, int32_t snap_every)
     HIP_TRY(c, hipEventDestroy(fork));
     return ADSCL_OK;
 }
+
+EvolveArgs evolve_args(adscl_ctx* c, int32_t snap_every)
+{
+    EvolveArgs a;
+    a.Phi = c->state5;
+    a.Pi = c->state5 + c->total;
+    a.A = c->state5 + 2 * c->total;
+    a.delta = c->state5 + 3 * c->total;
+    a.m = c->state5 + 4 * c->total;
+    a.ic = c->d_ic;
+    a.order = nullptr;
+    a.tab = c->d_tab;
+    a.status = c->d_status;
+    a.src = nullptr;
+    a.ckpt = nullptr;
+    a.total = c->total;
+    a.a_collapse = c->thr;
+    a.snap_every = snap_every;
+    a.gauge = c->gauge;
+    a.frozen = (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0;
+    a.ckpt_every = 0;
+    a.src_every = 1;
+    a.pad = 0;
+    return a;
+}
+
+// One segment of the fused kernel over all classes: every instance advances to
+// its target step, or to its next multiple of snap_every when that is > 0.
+int run_evolve(adscl_ctx* c, const EvolveArgs& base)
+{
+    return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
+        EvolveArgs a = base;
+        a.order = lc.d_order;
+        hipError_t e = hipSuccess;
+        if (lc.t0 && (e = hipEventRecord(lc.t0, s)) != hipSuccess) return e;
+        if ((e = launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s)) != hipSuccess) return e;
+        if (lc.t1) {
+            if ((e = hipEventRecord(lc.t1, s)) != hipSuccess) return e;
+            lc.timed = true;
+        }
+        return hipSuccess;
+    });
+}
+
+int run_evolve(adscl_ctx* c, int32_t snap_every) { return run_evolve(c, evolve_args(c, snap_every)); }
 
 int run_finalize(adscl_ctx* c, bool final, int32_t snap_every, int32_t n_slots, double* snaps)
 {
@@ -317,6 +366,20 @@ int after_init(adscl_ctx* c)
     if (rc) return rc;
     // solve the constraints at t = 0 (no step), flag collapsed / non-finite data
     if ((rc = run_finalize(c, true, 0, 0, nullptr))) return rc;
+    // Launch order within a class: longest expected run first.  Instances of
+    // one class share N, so their cost is set by how long they live; a smaller
+    // initial mass collapses later (or not at all), so it goes first.
+    std::vector<InstStatus> st(c->n_inst);
+    HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_status, sizeof(InstStatus) * c->n_inst, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (LaunchClass& lc : c->classes) {
+        std::stable_sort(lc.inst.begin(), lc.inst.end(), [&](int x, int y) {
+            if (c->N[x] != c->N[y]) return c->N[x] > c->N[y];
+            return st[x].mass < st[y].mass;
+        });
+        HIP_TRY(c, hipMemcpy(lc.d_order, lc.inst.data(), lc.inst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     c->initialized = true;
     return ADSCL_OK;
 }
@@ -420,6 +483,7 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
                 return bail(ADSCL_EUNSUPPORTED);
             }
             TRY_C(prepare_evolve(t.cfg, c->max_lds));
+            TRY_C(prepare_adjoint(t.cfg, c->max_lds));
             std::vector<double> tab, e, wpi, wphi;
             host_tables(N, t.cfg, tab);
             TRY_C(hipMalloc((void**)&t.d_tab, tab.size() * sizeof(double)));
@@ -523,6 +587,8 @@ void adscl_destroy(adscl_ctx* c)
     if (c->d_status) hipFree(c->d_status);
     if (c->d_ic) hipFree(c->d_ic);
     if (c->d_tmp) hipFree(c->d_tmp);
+    for (auto& kv : c->bufs)
+        if (kv.second.first) hipFree(kv.second.first);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -673,6 +739,176 @@ int adscl_spectrum(adscl_ctx* c, int32_t J, double* E, double* Pihat, double* Ph
         if (E) HIP_TRY(c, hipMemcpyAsync(E, dE, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         if (Pihat) HIP_TRY(c, hipMemcpyAsync(Pihat, dP, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         if (Phihat) HIP_TRY(c, hipMemcpyAsync(Phihat, dF, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return ADSCL_OK;
+}
+
+int adscl_adjoint(adscl_ctx* c, const double* eps, const double* coef, int32_t Jc, int32_t J, double T,
+                  int32_t ckpt_every, double* L, double* dLdc, int32_t* valid, int mem)
+{
+    if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
+    if (!eps || !coef || !L || !dLdc || !valid) return fail(c, ADSCL_EINVAL, "NULL argument");
+    if (c->flags & ADSCL_FROZEN_METRIC) return fail(c, ADSCL_EUNSUPPORTED, "adjoint needs the dynamic metric");
+    if (Jc < 1 || Jc > c->n_modes || J < 1 || J > c->n_modes)
+        return fail(c, ADSCL_EINVAL, "need 1 <= Jc, J <= n_modes");
+    if (!(T >= 0.0) || std::isinf(T)) return fail(c, ADSCL_EINVAL, "T must be finite and >= 0");
+    if (ckpt_every < 1) return fail(c, ADSCL_EINVAL, "ckpt_every must be >= 1");
+    if (int rc = check_mem(c, mem)) return rc;
+    const int n = c->n_inst;
+    const int64_t K = ckpt_every;
+    int rc;
+
+    // per-instance step counts and buffer sizes (doubles)
+    std::vector<int64_t> nf(n), ck_off(n + 1), seg_off(n + 1), stg_off(n + 1);
+    for (int b = 0; b < n; ++b) {
+        const double r = T / c->h_ic[b].dt - 1e-9;
+        nf[b] = (r <= 0.0) ? 0 : (int64_t)std::ceil(r);
+        const NTables& t = c->tables[c->N[b]];
+        ck_off[b + 1] = ck_off[b] + (nf[b] / K + 1) * 2 * (int64_t)c->N[b];
+        seg_off[b + 1] = seg_off[b] + (std::min<int64_t>(K, nf[b]) + 1) * 2 * (int64_t)c->N[b];
+        stg_off[b + 1] = stg_off[b] + (int64_t)adjoint_scratch_len(t.cfg);
+    }
+    void *ck, *seg, *stg, *ub, *u0, *dummy, *spec, *deps, *ptrs, *rst, *sgs, *outs;
+    const size_t nJ = (size_t)n * J;
+    if ((rc = buffer(c, "ckpt", sizeof(double) * ck_off[n], &ck))) return rc;
+    if ((rc = buffer(c, "seg", sizeof(double) * seg_off[n], &seg))) return rc;
+    if ((rc = buffer(c, "stage", sizeof(double) * stg_off[n], &stg))) return rc;
+    if ((rc = buffer(c, "ubar", sizeof(double) * 2 * c->total, &ub))) return rc;
+    if ((rc = buffer(c, "u0", sizeof(double) * 2 * c->total, &u0))) return rc;
+    if ((rc = buffer(c, "dummy", sizeof(double) * 2 * c->total, &dummy))) return rc;
+    if ((rc = buffer(c, "spec", sizeof(double) * 6 * nJ, &spec))) return rc;
+    if ((rc = buffer(c, "eps", sizeof(double) * n, &deps))) return rc;
+    if ((rc = buffer(c, "ptrs", sizeof(double*) * 3 * n, &ptrs))) return rc;
+    if ((rc = buffer(c, "rstatus", sizeof(InstStatus) * n, &rst))) return rc;
+    if ((rc = buffer(c, "segs", sizeof(AdjSeg) * n, &sgs))) return rc;
+    if ((rc = buffer(c, "outs", sizeof(double) * ((size_t)n * Jc + 2 * n), &outs))) return rc;
+    double* E0 = (double*)spec;
+    double* a0 = E0 + nJ;
+    double* b0 = a0 + nJ;
+    double* ET = b0 + nJ;
+    double* aT = ET + nJ;
+    double* bT = aT + nJ;
+    double** d_ckp = (double**)ptrs;
+    double** d_segp = d_ckp + n;
+    double** d_stgp = d_segp + n;
+    {
+        std::vector<double*> hp(3 * n);
+        for (int b = 0; b < n; ++b) {
+            hp[b] = (double*)ck + ck_off[b];
+            hp[n + b] = (double*)seg + seg_off[b];
+            hp[2 * n + b] = (double*)stg + stg_off[b];
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(ptrs, hp.data(), sizeof(double*) * 3 * n, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(c, hipMemcpyAsync(deps, eps, sizeof(double) * n,
+                              mem == ADSCL_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+
+    // forward: initial data, its spectrum, the evolution with checkpoints, the
+    // final spectrum
+    if ((rc = adscl_init_modes(c, eps, coef, Jc, mem))) return rc;
+    const double* s5 = c->state5;
+    HIP_TRY(c, hipMemcpyAsync(u0, s5, sizeof(double) * 2 * c->total, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, launch_spectrum(n, c->d_ic, s5, s5 + c->total, s5 + 2 * c->total, c->d_wPi, c->d_wPhi, J, E0, a0, b0,
+                               c->stream));
+    if ((rc = upload_ic(c, T))) return rc;
+    HIP_TRY(c, launch_set_targets(n, c->d_ic, c->d_status, INT64_MAX / 4, c->stream));
+    {
+        EvolveArgs a = evolve_args(c, 0);
+        a.ckpt = d_ckp;
+        a.ckpt_every = (int32_t)K;
+        if ((rc = run_evolve(c, a))) return rc;
+    }
+    if ((rc = run_finalize(c, true, 0, 0, nullptr))) return rc;
+    HIP_TRY(c, launch_spectrum(n, c->d_ic, s5, s5 + c->total, s5 + 2 * c->total, c->d_wPi, c->d_wPhi, J, ET, aT, bT,
+                               c->stream));
+
+    // reverse: final spectrum, segments from the last to the first, initial
+    // spectrum, initial map
+    HIP_TRY(c, hipMemsetAsync(ub, 0, sizeof(double) * 2 * c->total, c->stream));
+    EndArgs ea;
+    ea.ic = c->d_ic;
+    ea.order = nullptr;
+    ea.tab = c->d_tab;
+    ea.Phi = s5;
+    ea.Pi = s5 + c->total;
+    ea.wPi = c->d_wPi;
+    ea.wPhi = c->d_wPhi;
+    ea.Pihat = aT;
+    ea.Phihat = bT;
+    ea.E0 = E0;
+    ea.ET = ET;
+    ea.status = c->d_status;
+    ea.Ubar = (double*)ub;
+    ea.total = c->total;
+    ea.sgn = 1.0;
+    ea.J = J;
+    ea.gauge = c->gauge;
+    auto run_end = [&]() {
+        return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
+            EndArgs e = ea;
+            e.order = lc.d_order;
+            return launch_endpoint(lc.cfg, lc.full, (int)lc.inst.size(), e, s);
+        });
+    };
+    if ((rc = run_end())) return rc;
+
+    int64_t max_seg = 0;
+    for (int b = 0; b < n; ++b) max_seg = std::max<int64_t>(max_seg, (nf[b] + K - 1) / K);
+    EvolveArgs ra = evolve_args(c, 0);
+    ra.Phi = (double*)dummy;
+    ra.Pi = (double*)dummy + c->total;
+    ra.status = (InstStatus*)rst;
+    ra.src = d_ckp;
+    ra.src_every = (int32_t)K;
+    ra.ckpt = d_segp;
+    ra.ckpt_every = 1;
+    AdjointArgs aa;
+    aa.ic = c->d_ic;
+    aa.order = nullptr;
+    aa.tab = c->d_tab;
+    aa.seg = d_segp;
+    aa.stg = d_stgp;
+    aa.sg = (AdjSeg*)sgs;
+    aa.Ubar = (double*)ub;
+    aa.total = c->total;
+    aa.gauge = c->gauge;
+    aa.pad = 0;
+    for (int64_t r = 0; r < max_seg; ++r) {
+        HIP_TRY(c, launch_adj_prepare(n, c->d_ic, c->d_status, K, r, (InstStatus*)rst, (AdjSeg*)sgs, c->stream));
+        rc = run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
+            EvolveArgs e = ra;
+            e.order = lc.d_order;
+            hipError_t err = launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), e, s);
+            if (err != hipSuccess) return err;
+            AdjointArgs g = aa;
+            g.order = lc.d_order;
+            return launch_adjoint(lc.cfg, lc.full, (int)lc.inst.size(), g, s);
+        });
+        if (rc) return rc;
+    }
+    ea.Phi = (const double*)u0;
+    ea.Pi = (const double*)u0 + c->total;
+    ea.Pihat = a0;
+    ea.Phihat = b0;
+    ea.sgn = -1.0;
+    if ((rc = run_end())) return rc;
+
+    double* oL = (double*)outs;
+    double* oG = oL + n;
+    int32_t* oV = (int32_t*)(oG + (size_t)n * Jc);
+    if (mem == ADSCL_MEM_DEVICE) {
+        oL = L;
+        oG = dLdc;
+        oV = valid;
+    }
+    HIP_TRY(c, launch_adj_finish(n, c->d_ic, c->d_status, (const double*)ub, c->total, c->d_emode,
+                                 (const double*)deps, Jc, E0, ET, J, oL, oG, oV, c->stream));
+    if (mem == ADSCL_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(L, oL, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(dLdc, oG, sizeof(double) * n * Jc, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(valid, oV, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     return ADSCL_OK;

@@ -46,11 +46,19 @@ struct EvolveArgs {
     const int32_t* order;   // instance index per workgroup of this launch
     const double* const* tab;  // per instance: lane-interleaved tables of its class
     InstStatus* status;     // [n_inst]
+    // optional: per instance, stored states ([slot][2][N]: Phi then Pi, one
+    // every src_every steps) to start from, slot = n_start / src_every,
+    // instead of (Phi, Pi); and where to store the state every ckpt_every steps
+    // of the segment ([slot][2][N], slot = (n - n_start) / ckpt_every)
+    const double* const* src;
+    double* const* ckpt;
     int64_t total;
     double a_collapse;
     int32_t snap_every;     // > 0: stop each instance at the next multiple
     int32_t gauge;          // 0 boundary, 1 origin
     int32_t frozen;
+    int32_t ckpt_every;
+    int32_t src_every;
     int32_t pad;
 };
 
@@ -99,5 +107,68 @@ hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi
 hipError_t launch_spectrum(int n_inst, const InstConst* ic, const double* Phi, const double* Pi,
                            const double* A, const double* const* wPi, const double* const* wPhi, int J,
                            double* E, double* Pihat, double* Phihat, hipStream_t s);
+
+// ---- discrete adjoint -------------------------------------------------------
+
+// The steps [n0, n1) one reverse launch takes an instance through.
+struct AdjSeg {
+    int64_t n0;
+    int64_t n1;
+    int32_t active;
+    int32_t pad;
+};
+
+// Arguments of the reverse (adjoint) kernel: for every active instance, the
+// steps n1-1 down to n0 in reverse, each from its stored state U^t.
+struct AdjointArgs {
+    const InstConst* ic;
+    const int32_t* order;
+    const double* const* tab;
+    const double* const* seg;  // per instance: U^t for t = n0..n1, [t - n0][2][N]
+    double* const* stg;        // per instance: stage scratch, adjoint_scratch_len(cfg)
+    const AdjSeg* sg;          // [n_inst]
+    double* Ubar;              // packed adjoint state, [2][total], updated in place
+    int64_t total;
+    int32_t gauge;
+    int32_t pad;
+};
+
+// Arguments of the end-point kernel: adjoint of E_j = Pihat_j^2 + Phihat_j^2 and
+// of the constraint solve at a state, Ebar_j = 2 sgn (ET_j - E0_j), added to Ubar.
+struct EndArgs {
+    const InstConst* ic;
+    const int32_t* order;
+    const double* const* tab;
+    const double* Phi;         // packed state, [total]
+    const double* Pi;
+    const double* const* wPi;  // [Jtab][N] per instance
+    const double* const* wPhi;
+    const double* Pihat;       // [n_inst][J] at this state
+    const double* Phihat;
+    const double* E0;          // [n_inst][J]
+    const double* ET;
+    const InstStatus* status;  // instances in state DONE only
+    double* Ubar;
+    int64_t total;
+    double sgn;
+    int32_t J;
+    int32_t gauge;
+};
+
+size_t adjoint_scratch_len(ClassCfg c);
+hipError_t prepare_adjoint(ClassCfg c, size_t max_lds);
+hipError_t launch_adjoint(ClassCfg c, bool full, int n_blocks, const AdjointArgs& a, hipStream_t s);
+hipError_t launch_endpoint(ClassCfg c, bool full, int n_blocks, const EndArgs& a, hipStream_t s);
+// Segment r (counted from the end) of every instance that is DONE: recompute
+// status rst (steps n0, target n1; others COLLAPSED so the kernels skip them)
+// and the reverse range sg.
+hipError_t launch_adj_prepare(int n_inst, const InstConst* ic, const InstStatus* st, int64_t K, int64_t r,
+                              InstStatus* rst, AdjSeg* sg, hipStream_t s);
+// L_b = sum_j (ET - E0)^2; dL/dc_bk = eps_b sum_{i <= N-2} Pibar_i e_k(x_i) for
+// DONE instances (0 otherwise); valid_b = (state == DONE).
+hipError_t launch_adj_finish(int n_inst, const InstConst* ic, const InstStatus* st, const double* Ubar,
+                             int64_t total, const double* const* emode, const double* eps, int Jc,
+                             const double* E0, const double* ET, int J, double* L, double* dLdc,
+                             int32_t* valid, hipStream_t s);
 
 }  // namespace adscl

@@ -1,0 +1,412 @@
+// One workgroup's view of one instance during an RK4 stage of the AdS4
+// Einstein-Klein-Gordon evolution (Liebling & Khanna, arXiv:1706.07413,
+// Sec. II), shared by the forward evolution kernel and the reverse (adjoint)
+// kernel, which recomputes forward stages.
+//
+// Lane l of the workgroup owns the P consecutive grid points l*P .. l*P+P-1.
+// LDS rows are lane-interleaved: point j = l*P + k sits in row k, column l + 1,
+// so the P reads of a lane's own points and the reads of its neighbours' edge
+// points are consecutive across lanes (no bank conflicts).  Column 0 holds the
+// ghosts left of x = 0, column NL + 1 the points past the last lane (the end
+// point and its ghosts when N - 1 = 64 W P, "FULL").
+//
+// Prefix-sum form of the cell rule: with C_i = h(-u_{i-1}+13u_i+13u_{i+1}-u_{i+2})/24
+// and R_k = sum_{j<=k} u_j,
+//   sum_{i<k} C_i = h/24 (24 R_k - 12 u_k + u_{k-1} - u_{k+1} - u_{-1} - 12 u_0 + u_1),
+// the same sum of cells regrouped; for p (odd about 0, p_0 = 0) the last three
+// terms are 2 p_1, for sigma (even, sigma_0 = 0) they vanish.
+// The gauge shift is applied before the exponential: e^{-delta} with delta =
+// delta~ - delta~_{N-1} (boundary time, Eq. (12)) or delta = delta~ (origin
+// time); S, e^{-delta} and so A e^{-delta} scale consistently, and m = S/e^{-delta}
+// does not depend on the shift, so one exponential per point suffices.
+#pragma once
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace adscl {
+
+// Global-memory (address space 1) view of a device pointer.  A pointer read
+// from a per-instance pointer array is generic to the compiler, which then
+// emits flat memory instructions (64-bit VGPR addresses per access, counted
+// against the LDS wait counter as well); through this cast it emits global ones.
+#define ADSCL_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ ADSCL_GLOBAL T* gmem(T* p)
+{
+    return (ADSCL_GLOBAL T*)p;
+}
+
+// DPP move of a double: both 32-bit halves through the same data-parallel
+// primitive (lanes without a source read 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront: shifts by 1, 2, 4, 8
+// within rows of 16 lanes, then the row totals through the row broadcasts of
+// lanes 15 and 31 (gfx9 DPP row_shr / row_bcast).
+__device__ __forceinline__ double wave_incl_scan(double v)
+{
+    v += dpp_d<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_d<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_d<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_d<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+template <int P, int W>
+struct StageLayout {
+    static constexpr int NL = 64 * W;      // lanes per instance
+    static constexpr int RS = NL + 2;      // LDS row: column 0 = lane -1, NL+1 = lane NL
+    static constexpr int SLOTS = P * RS;
+    // U and F: 2 x SLOTS pairs; sigma edges: 2 NL; reductions: 4 W + 8
+    static constexpr size_t lds_doubles = (size_t)4 * SLOTS + 2 * NL + 4 * W + 8;
+};
+
+template <int P, int W, bool FULL>
+struct Stage {
+    static constexpr int NL = 64 * W;
+    static constexpr int RS = NL + 2;
+    static constexpr int SLOTS = P * RS;
+    static_assert(P >= 4, "lane 0 must own grid points 0..3");
+
+    double2* U;     // (Phi_s, Pi_s) rows
+    double2* F;     // (f1, g) rows; p first / last per lane between B0 and B2
+    double* PE;
+    double* SE;     // sigma first / last per lane
+    double* red;    // [0,W) delta~ totals, [W,2W) S totals, [2W,3W) flags,
+                    // [3W,4W) spare, 4W: p_1, 4W+1: p_{N-2}
+    int tid, lane, wv, i0, col, N;
+    bool has_nm2, near_end, bgauge;
+    double h, dt, h24, i12h, kof, thr;
+    const ADSCL_GLOBAL double* tab0;
+
+    __device__ __forceinline__ void setup(double* lds, const InstConst& ic, const double* tab, int gauge,
+                                          double a_collapse)
+    {
+        U = reinterpret_cast<double2*>(lds);
+        F = U + SLOTS;
+        // F is free from B0 (its last readers finished the previous stage)
+        // until the flux writes after B2
+        PE = reinterpret_cast<double*>(F);
+        SE = reinterpret_cast<double*>(F + SLOTS);
+        red = SE + 2 * NL;
+        tid = threadIdx.x;
+        lane = tid & 63;
+        wv = tid >> 6;
+        N = ic.N;
+        h = ic.h;
+        dt = ic.dt;
+        h24 = ic.h24;
+        i12h = ic.i12h;
+        kof = ic.kof;
+        thr = a_collapse;
+        bgauge = gauge == 0;
+        i0 = tid * P;
+        col = tid + 1;
+        // FULL: N - 1 == 64 W P, so every lane owns P evolved points and the
+        // last lane owns N-4..N-2; otherwise lanes past N-2 idle and the end moves.
+        has_nm2 = FULL ? (tid == NL - 1) : ((i0 <= N - 2) && (N - 2 < i0 + P));
+        near_end = FULL ? (tid == NL - 1) : ((i0 + P + 2 >= N - 4) && (i0 <= N - 2));
+        tab0 = gmem(tab);
+    }
+
+    __device__ __forceinline__ bool own(int k) const { return FULL || (i0 + k <= N - 2); }
+
+    // LDS index of point j, -P <= j < 64 W P + P
+    __device__ __forceinline__ int slot(int j) const
+    {
+        const int l = (j >= 0) ? (j / P) : -1 - ((-1 - j) / P);
+        return (j - l * P) * RS + l + 1;
+    }
+
+    // Per-stage view of the coefficient tables: a uniform base and the lane's
+    // byte offset, opaque to the compiler so that table loads are issued again
+    // in each stage (L2 hits) instead of being held in registers across the
+    // time loop, and take the scalar-base plus 32-bit vector-offset form.
+    struct TabView {
+        const ADSCL_GLOBAL char* base;
+        unsigned o;
+    };
+    __device__ __forceinline__ TabView tables() const
+    {
+        unsigned o = (unsigned)tid * 8u;
+        asm volatile("" : "+v"(o));
+        return TabView{(const ADSCL_GLOBAL char*)tab0, o};
+    }
+
+    // Table t (0 sin x cos x, 1 tan^2 x, 2 cot^2 x) at the lane's point k.
+    __device__ __forceinline__ double tab(const TabView& v, int t, int k) const
+    {
+        return *(const ADSCL_GLOBAL double*)(v.base + (v.o + (unsigned)((t * P + k) * NL * 8)));
+    }
+
+    // Publish (v0, v1) = (Phi, Pi) of the own points with parity ghosts:
+    // Phi odd / Pi even about x = 0, Phi even / Pi odd about pi/2, Phi = Pi = 0 at pi/2.
+    __device__ __forceinline__ void publish(const double* v0, const double* v1)
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (own(k)) U[k * RS + col] = make_double2(v0[k], v1[k]);
+        if (tid == 0) {
+            U[(P - 1) * RS] = make_double2(-v0[1], v1[1]);
+            U[(P - 2) * RS] = make_double2(-v0[2], v1[2]);
+            U[(P - 3) * RS] = make_double2(-v0[3], v1[3]);
+        }
+        if (FULL) {
+            if (tid == NL - 1) {
+                U[0 * RS + NL + 1] = make_double2(0.0, 0.0);
+                U[1 * RS + NL + 1] = make_double2(v0[P - 1], -v1[P - 1]);
+                U[2 * RS + NL + 1] = make_double2(v0[P - 2], -v1[P - 2]);
+                U[3 * RS + NL + 1] = make_double2(v0[P - 3], -v1[P - 3]);
+            }
+        } else if (near_end) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int j = i0 + k;
+                if (j >= N - 4 && j <= N - 2) U[slot(2 * (N - 1) - j)] = make_double2(v0[k], -v1[k]);
+            }
+            if (has_nm2) U[slot(N - 1)] = make_double2(0.0, 0.0);
+        }
+    }
+
+    // Constraint solve of the published state given q = Phi^2 + Pi^2 of the own
+    // points (Eqs. (5)-(6)): delta (gauge applied), e^{-delta} and S at own
+    // points, the delta~ end value dN and the S total tot2.  Contains barriers
+    // B1 and B2.
+    __device__ __forceinline__ void constraints(const double* q, double* dl, double* E, double* S, double& dN,
+                                                double& tot2)
+    {
+        const auto tb = tables();
+        double p[P];
+        double ptot = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            p[k] = tab(tb, 0, k) * q[k];  // table is 0 off 1..N-2
+            ptot += p[k];
+        }
+        const double incl = wave_incl_scan(ptot);
+        if (lane == 63) red[wv] = incl;
+        PE[tid] = p[0];
+        PE[NL + tid] = p[P - 1];
+        if (tid == 0) red[4 * W] = p[1];
+        if (FULL) {
+            if (tid == NL - 1) red[4 * W + 1] = p[P - 1];
+        } else if (has_nm2) {
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                if (i0 + k == N - 2) red[4 * W + 1] = p[k];
+        }
+        __syncthreads();  // B1
+        double carry = incl - ptot, tot = 0.0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            const double t = red[v];
+            if (v < wv) carry += t;
+            tot += t;
+        }
+        const double p1 = red[4 * W], pN2 = red[4 * W + 1];
+        const double pl = (tid > 0) ? PE[NL + tid - 1] : -p1;  // p_{-1} = -p_1
+        const double pr = (tid < NL - 1) ? PE[tid + 1] : 0.0;  // p_{N-1} = 0
+        dN = -h24 * (24.0 * tot + 2.0 * pN2 + 2.0 * p1);        // delta~_{N-1}
+        const double shift = bgauge ? dN : 0.0;
+
+        double sg[P];
+        double R = carry, stot = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            R += p[k];
+            const double pm = (k == 0) ? pl : p[k - 1];
+            const double pp = (k == P - 1) ? pr : p[k + 1];
+            const double dtil = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp + 2.0 * p1);
+            dl[k] = dtil - shift;
+            E[k] = exp(-dl[k]);
+            sg[k] = tab(tb, 1, k) * q[k] * E[k];  // table is 0 off 1..N-2
+            stot += sg[k];
+        }
+        const double incl2 = wave_incl_scan(stot);
+        if (lane == 63) red[W + wv] = incl2;
+        SE[tid] = sg[0];
+        SE[NL + tid] = sg[P - 1];
+        __syncthreads();  // B2
+        double carry2 = incl2 - stot;
+        tot2 = 0.0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            const double t = red[W + v];
+            if (v < wv) carry2 += t;
+            tot2 += t;
+        }
+        const double sl = (tid > 0) ? SE[NL + tid - 1] : sg[1];  // sigma_{-1} = sigma_1
+        const double sr = (tid < NL - 1) ? SE[tid + 1] : 0.0;    // sigma_{N-1} = 0
+        double R2 = carry2;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            R2 += sg[k];
+            const double sm = (k == 0) ? sl : sg[k - 1];
+            const double sp = (k == P - 1) ? sr : sg[k + 1];
+            S[k] = h24 * (24.0 * R2 - 12.0 * sg[k] + sm - sp);
+        }
+    }
+
+    // Right-hand sides of Eqs. (2)-(3) at the published stage input: barrier B0,
+    // Kreiss-Oliger terms and q from the +-3 window, the constraint solve (B1,
+    // B2), the fluxes f1 = A e^-delta Pi, g = tan^2 x A e^-delta Phi with parity
+    // ghosts (B3), the centred D stencil.  With `check`, the division-free test
+    // e^-delta - cos^3 x/sin x S < thr e^-delta (A < thr) and a finiteness test
+    // run before B3 and the function returns their workgroup-wide bits
+    // (1 collapsed, 2 non-finite) without computing r when any is set.
+    // r0, r1: Phi_t, Pi_t of the own points (0 at pinned points).  KEEP: also
+    // stores e^-delta and S of the lane's points to ES ([2][P][64 W], lane-interleaved).
+    template <bool KEEP = false>
+    __device__ __forceinline__ int rhs(bool check, bool frozen, double* r0, double* r1,
+                                       ADSCL_GLOBAL double* ES = nullptr)
+    {
+        __syncthreads();  // B0
+        const auto tb = tables();
+        double ko0[P], ko1[P], q[P];
+        {
+            double2 w[P + 6];                        // points i0-3 .. i0+P+2
+#pragma unroll
+            for (int t = 0; t < P + 6; ++t) {
+                const int tt = t - 3;
+                if (tt < 0) w[t] = U[(P + tt) * RS + col - 1];
+                else if (tt < P) w[t] = U[tt * RS + col];
+                else w[t] = U[(tt - P) * RS + col + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                ko0[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
+                                + 15.0 * w[k + 4].x - 6.0 * w[k + 5].x + w[k + 6].x);
+                ko1[k] = kof * (w[k].y - 6.0 * w[k + 1].y + 15.0 * w[k + 2].y - 20.0 * w[k + 3].y
+                                + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
+                // points past N-2 (general N only) may hold stale slots: keep them out
+                q[k] = own(k) ? w[k + 3].x * w[k + 3].x + w[k + 3].y * w[k + 3].y : 0.0;
+            }
+        }
+        double dl[P], E[P], S[P];
+        double dN = 0.0, tot2 = 0.0;
+        if (!frozen) {
+            constraints(q, dl, E, S, dN, tot2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
+        }
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                ES[k * NL + tid] = E[k];
+                ES[(P + k) * NL + tid] = S[k];
+            }
+        }
+
+        // fluxes; c3s and tan^2 x are 0 at x = 0 in the tables, so w_0 = E_0, g_0 = 0
+        double f2_1 = 0.0, f2_2 = 0.0, chk = 0.0;
+        double fl[3] = {0.0, 0.0, 0.0}, gl[3] = {0.0, 0.0, 0.0};  // f1, g at N-2, N-3, N-4 (FULL)
+        double f1a[3] = {0.0, 0.0, 0.0}, ga[3] = {0.0, 0.0, 0.0}; // f1, g at points 1, 2 (lane 0)
+        int cl = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int j = i0 + k;
+            if (own(k)) {
+                const double2 v = U[k * RS + col];
+                const double c3s = tab(tb, 2, k) * tab(tb, 0, k);
+                const double wk = E[k] - c3s * S[k];
+                const double f1 = wk * v.y;
+                const double f2 = wk * v.x;
+                const double g = tab(tb, 1, k) * f2;
+                if (k == 1) { f2_1 = f2; f1a[1] = f1; ga[1] = g; }
+                if (k == 2) { f2_2 = f2; f1a[2] = f1; ga[2] = g; }
+                if (k >= P - 3) { fl[P - 1 - k] = f1; gl[P - 1 - k] = g; }
+                if (check) {
+                    if (wk < thr * E[k]) cl = 1;
+                    chk = fma(q[k], 0.0, chk);
+                    chk = fma(wk, 0.0, chk);
+                    chk = fma(E[k], 0.0, chk);
+                }
+                F[k * RS + col] = make_double2(f1, g);
+                if (!FULL) {
+                    if (j >= N - 3 && j <= N - 2)    // f1 odd, g even about pi/2
+                        F[slot(2 * (N - 1) - j)] = make_double2(-f1, g);
+                }
+            }
+        }
+        if (tid == 0) {                              // f1 even, g odd about x = 0
+            F[(P - 1) * RS] = make_double2(f1a[1], -ga[1]);
+            F[(P - 2) * RS] = make_double2(f1a[2], -ga[2]);
+        }
+        if (FULL) {
+            if (tid == NL - 1) {
+                // f1_{N-1} = 0; g_{N-1} is the even 6th-order extrapolation of
+                // the finite limit at pi/2; then the ghosts N, N+1
+                F[0 * RS + NL + 1] = make_double2(0.0, (15.0 * gl[0] - 6.0 * gl[1] + gl[2]) / 10.0);
+                F[1 * RS + NL + 1] = make_double2(-fl[0], gl[0]);
+                F[2 * RS + NL + 1] = make_double2(-fl[1], gl[1]);
+            }
+        } else if (has_nm2) {
+            F[slot(N - 1)] = make_double2(0.0, 0.0);  // g_{N-1} set by the readers
+        }
+        if (check) {
+            if (1.0 < thr) cl = 1;
+            if (!isfinite(dN) || !isfinite(chk)) cl |= 2;
+            const int wcol = __any(cl & 1) ? 1 : 0;
+            const int wnf = __any(cl & 2) ? 2 : 0;
+            if (lane == 0) red[2 * W + wv] = (double)(wcol | wnf);
+        }
+        __syncthreads();  // B3
+        if (check) {
+            int fl_ = 0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) fl_ |= (int)red[2 * W + v];
+            if (fl_) return fl_;
+        }
+
+        double2 fw[P + 4];                           // points i0-2 .. i0+P+1
+#pragma unroll
+        for (int t = 0; t < P + 4; ++t) {
+            const int tt = t - 2;
+            if (tt < 0) fw[t] = F[(P + tt) * RS + col - 1];
+            else if (tt < P) fw[t] = F[tt * RS + col];
+            else fw[t] = F[(tt - P) * RS + col + 1];
+        }
+        if (!FULL && near_end) {
+            const int tN = (N - 1) - (i0 - 2);
+            if (tN >= 0 && tN < P + 4) {
+                const double gext = (15.0 * F[slot(N - 2)].y - 6.0 * F[slot(N - 3)].y + F[slot(N - 4)].y) / 10.0;
+#pragma unroll
+                for (int t = 0; t < P + 4; ++t)
+                    if (t == tN) fw[t].y = gext;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            // interior formula everywhere (cot^2 x is 0 at x = 0 in the table);
+            // the origin row and points past N-2 are fixed up below
+            const double Df1 = (fw[k].x - 8.0 * fw[k + 1].x + 8.0 * fw[k + 3].x - fw[k + 4].x) * i12h;
+            const double Dg = (fw[k].y - 8.0 * fw[k + 1].y + 8.0 * fw[k + 3].y - fw[k + 4].y) * i12h;
+            r0[k] = Df1 + ko0[k];
+            r1[k] = tab(tb, 2, k) * Dg + ko1[k];
+            if (k == 0 && tid == 0) {
+                // Phi_0 = 0; lim tan^-2 (tan^2 f2)' = 3 f2'(0) with f2 odd about x = 0
+                r0[k] = 0.0;
+                r1[k] = 3.0 * ((16.0 * f2_1 - 2.0 * f2_2) * i12h) + ko1[k];
+            }
+            if (!own(k)) {
+                r0[k] = 0.0;
+                r1[k] = 0.0;
+            }
+        }
+        return 0;
+    }
+};
+
+}  // namespace adscl
