@@ -34,10 +34,42 @@ FLOP_PER_PT_STAGE = 100.0
 BYTES_PER_PT_STEP = 32.0          # read (Phi, Pi)^n, write (Phi, Pi)^{n+1}
 PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector peak
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE
+# runs in profiles/evolve_batched1024_hbm.md (scaled by the copy calibration);
+# valid only for the kernel code those counters were taken on (empty while the
+# kernel has changed since).
+MEASURED_TRAFFIC = {}
 
 
 def pt_steps(N, steps):
     return float(np.sum(np.asarray(N, np.float64) * np.asarray(steps, np.float64)))
+
+
+def adjoint_rate(adscl, T, iters=2):
+    """Gradients per second of the batched descent loop: the 256-instance
+    mode-data draw (N in {2049, 4097}, 32 modes, drift of 16 modes,
+    checkpoints every 512 steps) over a window of T time units; each iteration
+    is one forward evolution and one reverse sweep of every instance, replayed
+    from a captured graph."""
+    import torch
+    from paper_1706_07413_amd import inputs as I
+    cfg = I.config4()
+    b = adscl.Batch(cfg["N"], gauge=cfg["gauge"], a_collapse=cfg["a_collapse"], n_modes=32)
+    eps = torch.tensor(cfg["eps"], dtype=torch.float64, device="cuda")
+    c = torch.tensor(cfg["c"], dtype=torch.float64, device="cuda")
+    b.descend(eps, c, cfg["J_obj"], T, 1, ckpt_every=cfg["ckpt_every"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist, active = b.descend(eps, c, cfg["J_obj"], T, iters, ckpt_every=cfg["ckpt_every"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(cfg["N"])
+    steps = np.ceil(T / (0.25 * (math.pi / 2) / (np.asarray(cfg["N"], np.float64) - 1)) - 1e-9)
+    return {"workload": "batched_adjoint_gd_256: 256 instances, N in {2049,4097}, eps log-U[0.02,0.2], 32 modes, "
+                        "J_obj 16, K 512, T=%g (window of the T=100 run), %d descent iterations" % (T, iters),
+            "grads_per_s": n * iters / dt, "s_per_iteration": dt / iters,
+            "forward_pt_steps_per_iteration": float(np.sum(steps * np.asarray(cfg["N"]))),
+            "active": int(active.sum().item())}
 
 
 def cpu_baseline(cfg, seconds):
@@ -81,6 +113,25 @@ def single_instance_rates(adscl, steps):
     return rates
 
 
+def large_instance_rate(adscl, steps=4096):
+    """The 16385-point two-mode instance (0.05 (e_0 + 0.6 e_1), boundary time)
+    alone on the GPU: 8 cooperating workgroups of 2048 points each."""
+    from paper_1706_07413_amd import inputs as I
+    cfg = I.config1()
+    b = adscl.Batch(cfg["N"], gauge=cfg["gauge"], a_collapse=cfg["a_collapse"], n_modes=2)
+    b.init_modes(cfg["eps"], np.ascontiguousarray(cfg["c"]))
+    b.step(64, 1e9)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps, 1e9)
+    b.sync()
+    dt = time.perf_counter() - t0
+    N = int(cfg["N"][0])
+    return {"workload": "single_twomode_N16385 (t=200 run), a window of %d RK4 steps" % steps,
+            "pt_steps_per_s": N * steps / dt, "us_per_step": dt / steps * 1e6,
+            "steps_per_s": steps / dt}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +142,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient-rate leg")
+    ap.add_argument("--adjoint-t", type=float, default=1.0, help="time window of the adjoint leg")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the workload, run a plain device copy of this many bytes "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -173,7 +226,8 @@ def main():
                    "pt_steps_per_pass": work / args.steps,
                    "collapsed": int(states[1]), "done": int(states[3]), "by_N": per_n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get((classes[k]["P"], classes[k]["W"])),
                      "kernel": "evolve_kernel<P=%d,W=%d> (%d instances)" % (classes[k]["P"], classes[k]["W"],
                                                                           classes[k]["members"]),
                      "launch_ms": ms, "flop_per_pt_stage": FLOP_PER_PT_STAGE},
@@ -187,6 +241,10 @@ def main():
         t_single = sum(float(per[N == n].sum()) / rates[n] for n in rates)
         out["single_instance"] = {"rates": {str(n): r for n, r in rates.items()},
                                   "batched_over_single": value / (work / args.steps / t_single)}
+    if not args.no_single:
+        out["large_instance"] = large_instance_rate(adscl)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_rate(adscl, args.adjoint_t)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out))

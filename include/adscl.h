@@ -10,8 +10,10 @@
  * and delta re-derived from the constraints Eqs. (5)-(6) at every stage, as two
  * prefix integrals over the grid.  All arithmetic is FP64.
  *
- * Layout: instance b has an odd grid size N_b (17 <= N_b <= 4097), h_b =
- * (pi/2)/(N_b-1), x_i = i h_b.  Every per-point array is packed: instance b
+ * Layout: instance b has an odd grid size N_b (17 <= N_b <= 65537), h_b =
+ * (pi/2)/(N_b-1), x_i = i h_b.  An instance with N_b <= 4097 is evolved by one
+ * workgroup; a larger one by several cooperating workgroups (chunks of 2048
+ * points, launched before the others in each call).  Every per-point array is packed: instance b
  * occupies [off_b, off_b + N_b) with off_b the exclusive prefix sum of N_b, in
  * the order the instances were given to adscl_create.
  *
@@ -65,7 +67,7 @@ enum { ADSCL_RUNNING = 0, ADSCL_COLLAPSED = 1, ADSCL_NONFINITE = 2, ADSCL_DONE =
 
 typedef struct {
     int32_t n_inst;          /* number of instances, >= 1                            */
-    const int32_t* n_grid;   /* host [n_inst]: N_b, odd, 17 <= N_b <= 4097            */
+    const int32_t* n_grid;   /* host [n_inst]: N_b, odd, 17 <= N_b <= 65537           */
     double cfl;              /* dt = cfl * h_b; default 0.25                          */
     double ko_sigma;         /* Kreiss-Oliger coefficient; default 0.5                */
     double a_collapse;       /* collapse threshold on min A (paper: 0.01)             */
@@ -105,7 +107,10 @@ int adscl_init_modes(adscl_ctx* ctx, const double* eps, const double* c, int32_t
  * Snapshots: when snap_every > 0 and n is a multiple of snap_every with slot
  * n / snap_every < n_snap_slots, (Phi, Pi, A, delta, m) of step n are written
  * to snaps[slot][field][sum N_b] (5 fields, m the mass function
- * (1-A) sin x / cos^3 x).  snaps may be NULL when snap_every == 0. */
+ * (1-A) sin x / cos^3 x).  snaps may be NULL when snap_every == 0.
+ * ADSCL_EHIP also when the workgroups of a large instance (N_b > 4097) stopped
+ * waiting for each other (a bounded wait of seconds; the instance is then left
+ * NONFINITE with t_collapse = -2). */
 int adscl_step(adscl_ctx* ctx, int64_t max_steps, double t_end, int32_t snap_every,
                int32_t n_snap_slots, double* snaps, int mem);
 
@@ -132,6 +137,13 @@ int adscl_constraints(adscl_ctx* ctx, double* out, int mem);
  * give NaN. */
 int adscl_spectrum(adscl_ctx* ctx, int32_t J, double* E, double* Pihat, double* Phihat, int mem);
 
+/* The same mode energies for n_slots stored states, e.g. the snapshots
+ * adscl_step wrote: snaps [n_slots][5][sum N_b] (Phi, Pi, A, delta, m rows;
+ * only Phi, Pi and A are read).  Outputs [n_slots x n_inst x J].  All states
+ * of one grid size form a single (states x N) . (N x J) FP64 matrix product. */
+int adscl_spectrum_snaps(adscl_ctx* ctx, int32_t J, int32_t n_slots, const double* snaps, double* E,
+                         double* Pihat, double* Phihat, int mem);
+
 /* Gradient of the drift of the low mode energies by the discrete adjoint of the
  * whole computation (Sec. II: data from a mode spectrum, evolution, normal-mode
  * decomposition).  For every instance b:
@@ -154,6 +166,26 @@ int adscl_spectrum(adscl_ctx* ctx, int32_t J, double* E, double* Pihat, double* 
  * adscl_init_modes followed by adscl_step to T would leave it. */
 int adscl_adjoint(adscl_ctx* ctx, const double* eps, const double* c, int32_t Jc, int32_t J, double T,
                   int32_t ckpt_every, double* L, double* dLdc, int32_t* valid, int mem);
+/* (adscl_adjoint and adscl_descend: ADSCL_EUNSUPPORTED when an instance has
+ * N_b > 4097.) */
+
+/* Batched gradient descent on the drift objective of adscl_adjoint (one
+ * forward evolution and one reverse sweep per iteration for every instance).
+ * Per instance b with step fraction s_b = step0 at the start, iteration i:
+ *   (L_b, g_b) as adscl_adjoint at the current c_b; L_hist[i][b] = L_b;
+ *   if the evolution of b collapsed or went non-finite, b is masked: c_b stays,
+ *   active_b = 0, and it is skipped (L_hist = NaN) for the remaining iterations;
+ *   otherwise, if L_b exceeds its value at the previous iteration, s_b is halved,
+ *   and c_b <- c_b - s_b |c_b| / |g_b| g_b (Euclidean norms; no change if g_b = 0).
+ * c [n_inst x Jc] is read and overwritten with the final coefficients; L_hist
+ * [iters x n_inst]; active [n_inst] (int32).  Other arguments as adscl_adjoint;
+ * iters >= 1, step0 > 0.  One iteration is captured into a HIP graph once and
+ * replayed `iters` times; ADSCL_DESCEND_EAGER enqueues every iteration
+ * directly instead (same results, bit for bit). */
+enum { ADSCL_DESCEND_EAGER = 1 };
+int adscl_descend(adscl_ctx* ctx, const double* eps, double* c, int32_t Jc, int32_t J, double T,
+                  int32_t ckpt_every, int32_t iters, double step0, int32_t flags, double* L_hist,
+                  int32_t* active, int mem);
 
 /* Block until all work enqueued on the context's stream is done. */
 int adscl_sync(adscl_ctx* ctx);

@@ -239,6 +239,45 @@ def objective(N, eps, c, T=None, n_steps=None, J=16, K=512, gauge=GAUGE_BOUNDARY
                 n_steps=int(n_steps))
 
 
+def descend(Ns, eps, c, J, T, K, iters, step0, gauge=GAUGE_BOUNDARY, a_collapse=0.0):
+    """Batched gradient descent on the drift objective (the scheme's objective
+    has no descent rule in the paper; this is the rule the library documents):
+    per instance, step fraction s = step0; each iteration takes (L, g) from
+    ``objective``; an instance whose evolution collapses is masked from then on
+    (c kept, later L entries NaN); otherwise s halves when L grew since the
+    previous iteration and c <- c - s |c| / |g| g.  Plain loops, sums in index
+    order.  Returns (c, L_hist [iters x n], active [n])."""
+    c = np.array(c, dtype=np.float64, copy=True)
+    n = len(Ns)
+    s = [float(step0)] * n
+    Lprev = [math.inf] * n
+    active = [1] * n
+    hist = np.full((iters, n), np.nan)
+    for it in range(iters):
+        for b in range(n):
+            if not active[b]:
+                continue
+            r = objective(int(Ns[b]), float(eps[b]), c[b], T=T, J=J, K=K, gauge=gauge, a_collapse=a_collapse)
+            hist[it, b] = r["L"]
+            if not r["valid"]:
+                active[b] = 0
+                continue
+            if r["L"] > Lprev[b]:
+                s[b] *= 0.5
+            Lprev[b] = r["L"]
+            g = r["grad"]
+            cn = 0.0
+            gn = 0.0
+            for k in range(c.shape[1]):
+                cn += c[b, k] * c[b, k]
+                gn += g[k] * g[k]
+            if gn > 0.0:
+                f = s[b] * math.sqrt(cn) / math.sqrt(gn)
+                for k in range(c.shape[1]):
+                    c[b, k] -= f * g[k]
+    return c, hist, np.array(active, np.int32)
+
+
 def constraints_vjp(Phi, Pi, Abar, dbar, gauge=GAUGE_BOUNDARY):
     lib = _load()
     Phi, Pi, Abar, dbar = map(_f64, (Phi, Pi, Abar, dbar))

@@ -18,12 +18,13 @@ GAUGE_BOUNDARY, GAUGE_ORIGIN = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 FROZEN_METRIC = 1
 TIME_KERNELS = 2
+DESCEND_EAGER = 1
 RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
 
 # Every function include/adscl.h declares.
 EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
-           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum",
-           "adscl_adjoint", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error")
+           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum", "adscl_spectrum_snaps",
+           "adscl_adjoint", "adscl_descend", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error")
 
 
 class AdsclError(RuntimeError):
@@ -64,7 +65,10 @@ def lib():
         "adscl_status": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "adscl_constraints": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
         "adscl_spectrum": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_int]),
+        "adscl_spectrum_snaps": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_int]),
         "adscl_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _d, _i32, _vp, _vp, _vp, ctypes.c_int]),
+        "adscl_descend": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _d, _i32, _i32, _d, _i32, _vp, _vp,
+                                         ctypes.c_int]),
         "adscl_sync": (ctypes.c_int, [_vp]),
         "adscl_layout": (ctypes.c_int, [_vp, _vp, _vp]),
         "adscl_kernel_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -204,6 +208,21 @@ class Batch:
         self._check(lib().adscl_spectrum(self._h, int(J), E.ctypes.data, P.ctypes.data, F.ctypes.data, MEM_HOST))
         return E, P, F
 
+    def spectrum_snaps(self, J, snaps):
+        """Mode energies of stored states snaps [slots, 5, total] (numpy or
+        torch); returns E, Pihat, Phihat [slots, n_inst, J] of the same kind."""
+        p, m = _ptr_mem(snaps)
+        S = int(snaps.shape[0])
+        if m == MEM_DEVICE:
+            import torch
+            outs = [torch.empty((S, self.n_inst, J), dtype=torch.float64, device=snaps.device) for _ in range(3)]
+        else:
+            outs = [np.zeros((S, self.n_inst, J)) for _ in range(3)]
+        self._check(lib().adscl_spectrum_snaps(self._h, int(J), S, p, *[_ptr_mem(o)[0] for o in outs], m))
+        if m == MEM_DEVICE:
+            self.sync()
+        return tuple(outs)
+
     def adjoint(self, eps, c, J, T, ckpt_every=512):
         """Drift objective L_b = sum_{j<J} (E_j(T) - E_j(0))^2 of mode-sum data
         eps_b sum_k c_bk e_k and its gradient dL_b/dc_b (adscl_adjoint).  Host
@@ -228,6 +247,30 @@ class Batch:
         if me == MEM_DEVICE:
             self.sync()
         return L, g, v
+
+    def descend(self, eps, c, J, T, iters, step0=0.05, ckpt_every=512, eager=False):
+        """Batched gradient descent on the drift objective (adscl_descend).
+        Returns (c_final, L_hist [iters x n_inst], active) of the kind of c
+        (numpy on the host, torch on the device); c itself is not modified."""
+        n, Jc = self.n_inst, int(c.shape[1])
+        pe, me = _ptr_mem(eps)
+        if me == MEM_DEVICE:
+            import torch
+            cw = c.clone()
+            hist = torch.empty((iters, n), dtype=torch.float64, device=c.device)
+            act = torch.empty(n, dtype=torch.int32, device=c.device)
+            pa = act.data_ptr()
+        else:
+            cw = np.array(c, dtype=np.float64, copy=True)
+            hist = np.zeros((iters, n))
+            act = np.zeros(n, np.int32)
+            pa = act.ctypes.data
+        self._check(lib().adscl_descend(self._h, pe, _ptr_mem(cw)[0], Jc, int(J), float(T), int(ckpt_every),
+                                        int(iters), float(step0), DESCEND_EAGER if eager else 0,
+                                        _ptr_mem(hist)[0], pa, me))
+        if me == MEM_DEVICE:
+            self.sync()
+        return cw, hist, act
 
     def kernel_stats(self):
         """Launch classes: list of dicts (P, W, members, last_ms) and the class

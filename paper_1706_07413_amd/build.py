@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadscl.so")
 ARCH = os.environ.get("ADSCL_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["evolve.hip", "adjoint.hip", "aux.hip", "spectrum.hip", "api.cpp"]
+SOURCES = ["evolve.hip", "evolve_big.hip", "adjoint.hip", "aux.hip", "spectrum.hip", "api.cpp"]
 
 
 def hipcc():

@@ -24,8 +24,9 @@ namespace {
 
 // Fields of the per-instance stage scratch, each [P][64 W]: stage s holds
 // Phi_s, Pi_s, e^-delta_s, S_s at 4 s .. 4 s + 3; then the adjoint state at the
-// start of the step's reverse (Phibar', Pibar').
-constexpr int kFields = 18;
+// start of the step's reverse (Phibar', Pibar': 16, 17) and the running adjoint
+// state (18, 19).
+constexpr int kFields = 20;
 
 template <int P, int W, bool FULL>
 struct Rev {
@@ -41,8 +42,10 @@ struct Rev {
     //   dt_k = -h/24 (24 R_k - 12 p_k + p_{k-1} - p_{k+1} + 2 p_1), p = sin x cos x q.
     // Non-own points must carry Eb = Sb = 0.  The LDS edge and reduction slots
     // must be free on entry; contains two barriers.
-    static __device__ __forceinline__ void constraint_reverse(S_t& sg, const double* v0, const double* v1,
-                                                              const double* E, double* Eb, const double* Sb,
+    // `val(f, k)` gives Phi (f = 0), Pi (1) and e^-delta (2) of the state at the
+    // lane's point k (re-read where needed rather than held across the scans).
+    template <class V>
+    static __device__ __forceinline__ void constraint_reverse(S_t& sg, V&& val, double* Eb, const double* Sb,
                                                               double* vb0, double* vb1)
     {
         const auto tb = sg.tables();
@@ -78,11 +81,12 @@ struct Rev {
             const double sp = (k == P - 1) ? sr : Sb[k + 1];
             const double sb = h24 * (24.0 * suf - 12.0 * Sb[k] + sp - sm);
             const double t2 = sg.tab(tb, 1, k);
-            const double q = v0[k] * v0[k] + v1[k] * v1[k];
-            qb[k] = sg.own(k) ? t2 * E[k] * sb : 0.0;
+            const double v0 = val(0, k), v1 = val(1, k), Ek = val(2, k);
+            const double q = v0 * v0 + v1 * v1;
+            qb[k] = sg.own(k) ? t2 * Ek * sb : 0.0;
             const double eb = Eb[k] + (sg.own(k) ? t2 * q * sb : 0.0);
             // cotangent of dt_k; dt_0 is identically 0, its share goes to the shift only
-            const double dk = sg.own(k) ? -E[k] * eb : 0.0;
+            const double dk = sg.own(k) ? -Ek * eb : 0.0;
             if (k == 0 && tid == 0) {
                 d0 = dk;
                 d[k] = 0.0;
@@ -126,8 +130,8 @@ struct Rev {
             pb += shb * (-h24 * ws);
             const double q2 = qb[k] + sg.tab(tb, 0, k) * pb;  // table is 0 off 1..N-2
             if (sg.own(k)) {
-                vb0[k] += 2.0 * v0[k] * q2;
-                vb1[k] += 2.0 * v1[k] * q2;
+                vb0[k] += 2.0 * val(0, k) * q2;
+                vb1[k] += 2.0 * val(1, k) * q2;
             }
         }
     }
@@ -135,7 +139,7 @@ struct Rev {
     // Adjoint of one stage map V -> k = (Phi_t, Pi_t)(V): given the cotangents
     // (kb0, kb1) of k at the own points, returns (vb0, vb1) = J^T kb.  V, e^-delta
     // and S of the stage come from the scratch fields f0 .. f0+3.
-    static __device__ __forceinline__ void stage_reverse(S_t& sg, const ADSCL_GLOBAL double* stg, int f0,
+    static __device__ __forceinline__ void stage_reverse(S_t& sg, ADSCL_GLOBAL double* stg, int f0,
                                                          const double* kb0,
                                                          const double* kb1, double* vb0, double* vb1)
     {
@@ -191,14 +195,6 @@ struct Rev {
                 else if (tt < P) w[t] = U[tt * RS + col];
                 else w[t] = U[(tt - P) * RS + col + 1];
             }
-            double fw[P + 4];  // points i0-2 .. i0+P+1
-#pragma unroll
-            for (int t = 0; t < P + 4; ++t) {
-                const int tt = t - 2;
-                if (tt < 0) fw[t] = F[(P + tt) * RS + col - 1].x;
-                else if (tt < P) fw[t] = F[tt * RS + col].x;
-                else fw[t] = F[(tt - P) * RS + col + 1].x;
-            }
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 // the Kreiss-Oliger stencil is symmetric: its transpose is itself
@@ -208,8 +204,19 @@ struct Rev {
                                 + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
                 // D is antisymmetric: its transpose is -D
                 f1b[k] = (w[k + 5].x - 8.0 * w[k + 4].x + 8.0 * w[k + 2].x - w[k + 1].x) * i12h;
-                gb[k] = (fw[k + 4] - 8.0 * fw[k + 3] + 8.0 * fw[k + 1] - fw[k]) * i12h;
             }
+        }
+        {
+            double fw[P + 4];  // points i0-2 .. i0+P+1
+#pragma unroll
+            for (int t = 0; t < P + 4; ++t) {
+                const int tt = t - 2;
+                if (tt < 0) fw[t] = F[(P + tt) * RS + col - 1].x;
+                else if (tt < P) fw[t] = F[tt * RS + col].x;
+                else fw[t] = F[(tt - P) * RS + col + 1].x;
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) gb[k] = (fw[k + 4] - 8.0 * fw[k + 3] + 8.0 * fw[k + 1] - fw[k]) * i12h;
         }
         // rows whose stencils reach the ghosts left of x = 0 (Phi odd, Pi even,
         // f1 even, g odd) and the origin row Pi_t(0) = 3 D f2(0) + KO Pi
@@ -251,27 +258,28 @@ struct Rev {
             }
         }
 
-        double v0[P], v1[P], E[P], Eb[P], Sb[P];
+        // stage values, re-read from the scratch where they are used
+        double Eb[P], Sb[P];
+        {
+            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const size_t ix = (size_t)k * NL + tid;
-            v0[k] = stg[(size_t)(f0 + 0) * P * NL + ix];
-            v1[k] = stg[(size_t)(f0 + 1) * P * NL + ix];
-            E[k] = stg[(size_t)(f0 + 2) * P * NL + ix];
-            const double S = stg[(size_t)(f0 + 3) * P * NL + ix];
+            for (int k = 0; k < P; ++k) {
+                const double v0 = sv.ld(f0, k), v1 = sv.ld(f0 + 1, k), E = sv.ld(f0 + 2, k), S = sv.ld(f0 + 3, k);
             double f2b = sg.tab(tb, 1, k) * gb[k];
             if (tid == 0 && k == 1) f2b += 16.0 * ob;
             if (tid == 0 && k == 2) f2b -= 2.0 * ob;
             const double c3s = sg.tab(tb, 2, k) * sg.tab(tb, 0, k);
-            const double wk = E[k] - c3s * S;
-            const double wb = v1[k] * f1b[k] + v0[k] * f2b;
+            const double wk = E - c3s * S;
+            const double wb = v1 * f1b[k] + v0 * f2b;
             const bool o = sg.own(k);
             vb0[k] = o ? koa[k] + wk * f2b : 0.0;
             vb1[k] = o ? kob[k] + wk * f1b[k] : 0.0;
             Eb[k] = o ? wb : 0.0;
             Sb[k] = o ? -c3s * wb : 0.0;
+            }
         }
-        constraint_reverse(sg, v0, v1, E, Eb, Sb, vb0, vb1);
+        constraint_reverse(
+            sg, [&](int f, int k) -> double { return lane_arr<P, NL>(stg, tid).ld(f0 + f, k); }, Eb, Sb, vb0, vb1);
         if (tid == 0) vb0[0] = 0.0;  // Phi_0 is pinned
     }
 };
@@ -291,64 +299,79 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
     const int N = sg.N, i0 = sg.i0, tid = sg.tid;
     const double dt = sg.dt;
     ADSCL_GLOBAL double* const stg = gmem(a.stg[b]);
-    auto at = [&](int f, int k) -> size_t { return ((size_t)f * P + k) * NL + tid; };
 
-    double ub0[P], ub1[P];
+    {
+        const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const bool o = sg.own(k);
-        ub0[k] = o ? a.Ubar[ic.off + i0 + k] : 0.0;
-        ub1[k] = o ? a.Ubar[a.total + ic.off + i0 + k] : 0.0;
+        for (int k = 0; k < P; ++k) {
+            const bool o = sg.own(k);
+            sv.st(18, k, o ? a.Ubar[ic.off + i0 + k] : 0.0);
+            sv.st(19, k, o ? a.Ubar[a.total + ic.off + i0 + k] : 0.0);
+        }
     }
 
     for (int64_t t = sq.n1 - 1; t >= sq.n0; --t) {
-        // the adjoint state at the start of this step's reverse (U-bar') waits in
-        // the scratch while the forward pass needs the registers
+        // the adjoint state at the start of this step's reverse, U-bar'
+        {
+            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            stg[at(16, k)] = ub0[k];
-            stg[at(17, k)] = ub1[k];
+            for (int k = 0; k < P; ++k) {
+                sv.st(16, k, sv.ld(18, k));
+                sv.st(17, k, sv.ld(19, k));
+            }
         }
         // forward: the stage inputs V_s of step t and their e^-delta and S
         {
             const ADSCL_GLOBAL double* u = gmem(a.seg[b]) + (size_t)(t - sq.n0) * 2 * (size_t)N;
             double un0[P], un1[P];
+            {
+                const auto sv = lane_arr<P, NL>(stg, tid);
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const bool o = sg.own(k);
+                    un0[k] = o ? u[i0 + k] : 0.0;
+                    un1[k] = o ? u[N + i0 + k] : 0.0;
+                    sv.st(0, k, un0[k]);
+                    sv.st(1, k, un1[k]);
+                }
+            }
+            // the reverse sweep's last readers of the LDS edges are done
+            __syncthreads();
+            sg.publish(un0, un1);
+            double cv0[P], cv1[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const bool o = sg.own(k);
-                un0[k] = o ? u[i0 + k] : 0.0;
-                un1[k] = o ? u[N + i0 + k] : 0.0;
-                stg[at(0, k)] = un0[k];
-                stg[at(1, k)] = un1[k];
+                cv0[k] = un0[k];
+                cv1[k] = un1[k];
             }
-            sg.publish(un0, un1);
 #pragma unroll 1
             for (int s = 0; s < 4; ++s) {
                 double r0[P], r1[P];
-                sg.template rhs<true>(false, false, r0, r1, stg + (size_t)(4 * s + 2) * P * NL);
+                sg.template rhs<true>(false, false, cv0, cv1, r0, r1, stg, 4 * s + 2);
                 if (s < 3) {
                     const double c_next = (s == 2) ? dt : 0.5 * dt;
-                    double us0[P], us1[P];
+                    const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
-                        us0[k] = un0[k] + c_next * r0[k];
-                        us1[k] = un1[k] + c_next * r1[k];
-                        stg[at(4 * (s + 1), k)] = us0[k];
-                        stg[at(4 * (s + 1) + 1, k)] = us1[k];
+                        cv0[k] = un0[k] + c_next * r0[k];
+                        cv1[k] = un1[k] + c_next * r1[k];
+                        sv.st(4 * (s + 1), k, cv0[k]);
+                        sv.st(4 * (s + 1) + 1, k, cv1[k]);
                     }
-                    sg.publish(us0, us1);
+                    sg.publish(cv0, cv1);
                 }
             }
         }
         // reverse of U' = U + dt sum_s b_s k_s with stage inputs V_s = U + c_s dt k_{s-1}:
         // kbar_s = dt b_s U-bar' + c_{s+1} dt Vbar_{s+1}, U-bar = U-bar' + sum_s Vbar_s
         double kb0[P], kb1[P];
+        {
+            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            ub0[k] = stg[at(16, k)];
-            ub1[k] = stg[at(17, k)];
-            kb0[k] = (dt / 6.0) * ub0[k];
-            kb1[k] = (dt / 6.0) * ub1[k];
+            for (int k = 0; k < P; ++k) {
+                kb0[k] = (dt / 6.0) * sv.ld(16, k);
+                kb1[k] = (dt / 6.0) * sv.ld(17, k);
+            }
         }
 #pragma unroll 1
         for (int s = 3; s >= 0; --s) {
@@ -356,20 +379,24 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
             R::stage_reverse(sg, stg, 4 * s, kb0, kb1, vb0, vb1);
             const double cs = (s == 3) ? dt : 0.5 * dt;
             const double bp = (s == 1) ? dt / 6.0 : dt / 3.0;
+            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                ub0[k] += vb0[k];
-                ub1[k] += vb1[k];
-                kb0[k] = bp * stg[at(16, k)] + cs * vb0[k];
-                kb1[k] = bp * stg[at(17, k)] + cs * vb1[k];
+                sv.st(18, k, sv.ld(18, k) + vb0[k]);
+                sv.st(19, k, sv.ld(19, k) + vb1[k]);
+                kb0[k] = bp * sv.ld(16, k) + cs * vb0[k];
+                kb1[k] = bp * sv.ld(17, k) + cs * vb1[k];
             }
         }
     }
+    {
+        const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        if (sg.own(k)) {
-            a.Ubar[ic.off + i0 + k] = ub0[k];
-            a.Ubar[a.total + ic.off + i0 + k] = ub1[k];
+        for (int k = 0; k < P; ++k) {
+            if (sg.own(k)) {
+                a.Ubar[ic.off + i0 + k] = sv.ld(18, k);
+                a.Ubar[a.total + ic.off + i0 + k] = sv.ld(19, k);
+            }
         }
     }
 }
@@ -380,7 +407,6 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
 template <int P, int W, bool FULL>
 __global__ void __launch_bounds__(64 * W) endpoint_kernel(EndArgs a)
 {
-    constexpr int NL = 64 * W;
     using R = Rev<P, W, FULL>;
     extern __shared__ double lds[];
     const int b = a.order[blockIdx.x];
@@ -438,7 +464,8 @@ __global__ void __launch_bounds__(64 * W) endpoint_kernel(EndArgs a)
         Sb[k] = o ? -c3s * Ab / E[k] : 0.0;
     }
     __syncthreads();  // the solve's readers of the edge and reduction slots are done
-    R::constraint_reverse(sg, v0, v1, E, Eb, Sb, vb0, vb1);
+    R::constraint_reverse(
+        sg, [&](int f, int k) -> double { return f == 0 ? v0[k] : (f == 1 ? v1[k] : E[k]); }, Eb, Sb, vb0, vb1);
     if (tid == 0) vb0[0] = 0.0;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -506,6 +533,73 @@ __global__ void __launch_bounds__(256) adj_finish_kernel(int n_inst, const InstC
         L[b] = l;
         valid[b] = ok ? 1 : 0;
     }
+}
+
+// Device fill (used instead of a memset so that the enqueue sequence can be
+// captured into a graph).
+__global__ void fill_kernel(double* p, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void mask_kernel(int n_inst, InstStatus* st, const int32_t* active)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_inst || active[b]) return;
+    InstStatus o = st[b];
+    o.state = ST_COLLAPSED;
+    st[b] = o;
+}
+
+__global__ void gd_init_kernel(int n_inst, double step0, GdState g)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) g.iter[0] = 0;
+    if (b >= n_inst) return;
+    g.s[b] = step0;
+    g.Lprev[b] = INFINITY;
+    g.active[b] = 1;
+}
+
+// One thread per instance: the descent step of iteration g.iter[0].
+__global__ void gd_update_kernel(int n_inst, int Jc, double* c, const double* grad, const double* L,
+                                 const int32_t* valid, GdState g, double* L_hist)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_inst) return;
+    const int it = g.iter[0];
+    double* lh = L_hist + (size_t)it * n_inst + b;
+    if (!g.active[b]) {
+        *lh = NAN;
+        return;
+    }
+    const double l = L[b];
+    *lh = l;
+    if (!valid[b]) {
+        g.active[b] = 0;
+        return;
+    }
+    double s = g.s[b];
+    if (l > g.Lprev[b]) s *= 0.5;
+    g.s[b] = s;
+    g.Lprev[b] = l;
+    double* cb = c + (size_t)b * Jc;
+    const double* gb = grad + (size_t)b * Jc;
+    double cn = 0.0, gn = 0.0;
+    for (int k = 0; k < Jc; ++k) {
+        cn += cb[k] * cb[k];
+        gn += gb[k] * gb[k];
+    }
+    if (gn > 0.0) {
+        const double f = s * sqrt(cn) / sqrt(gn);
+        for (int k = 0; k < Jc; ++k) cb[k] -= f * gb[k];
+    }
+}
+
+__global__ void gd_tick_kernel(GdState g)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) g.iter[0] += 1;
 }
 
 template <int P, int W>
@@ -599,6 +693,37 @@ hipError_t launch_adj_prepare(int n_inst, const InstConst* ic, const InstStatus*
                               InstStatus* rst, AdjSeg* sg, hipStream_t s)
 {
     adj_prepare_kernel<<<dim3((n_inst + 255) / 256), dim3(256), 0, s>>>(n_inst, ic, st, K, r, rst, sg);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    fill_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask(int n_inst, InstStatus* st, const int32_t* active, hipStream_t s)
+{
+    mask_kernel<<<dim3((n_inst + 255) / 256), dim3(256), 0, s>>>(n_inst, st, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd_init(int n_inst, double step0, const GdState& g, hipStream_t s)
+{
+    gd_init_kernel<<<dim3((n_inst + 255) / 256), dim3(256), 0, s>>>(n_inst, step0, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd_update(int n_inst, int Jc, double* c, const double* grad, const double* L, const int32_t* valid,
+                            const GdState& g, double* L_hist, hipStream_t s)
+{
+    gd_update_kernel<<<dim3((n_inst + 255) / 256), dim3(256), 0, s>>>(n_inst, Jc, c, grad, L, valid, g, L_hist);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    gd_tick_kernel<<<dim3(1), dim3(64), 0, s>>>(g);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,6 +21,8 @@ using namespace adscl;
 namespace {
 
 thread_local std::string g_create_error;
+constexpr int kMaxN = 65537;       // largest grid
+constexpr int kMaxOneGroup = 4097;  // largest grid one workgroup holds
 
 // One launch of the fused kernel: a (P, W) configuration, whether all its
 // instances fill it exactly, and its instances in launch order.
@@ -32,6 +35,11 @@ struct LaunchClass {
     hipEvent_t done = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;  // timing (ADSCL_TIME_KERNELS)
     bool timed = false;
+    // one large instance over `chunks` workgroups (0: one workgroup per instance)
+    int chunks = 0;
+    double* xch = nullptr;              // exchange records [chunks][32]
+    unsigned long long* ctr = nullptr;  // arrival counter, then the error flag
+    int* err = nullptr;
 };
 
 // Host-side tables of one grid size N.
@@ -72,6 +80,13 @@ struct adscl_ctx {
     size_t tmp_bytes = 0;
     // adjoint working memory, kept for reuse by later calls
     std::map<std::string, std::pair<void*, size_t>> bufs;
+    hipEvent_t fork = nullptr;  // start of a multi-class launch, recorded on `stream`
+    int n_big = 0;              // classes holding one large (multi-workgroup) instance
+    // spectrum rows for states laid out as [slot][5][total], grouped by N:
+    // (N, first row, rows) per group, for spec_slots slots
+    int spec_slots = -1;
+    std::vector<std::array<int, 3>> spec_groups;
+    SpecRow* d_spec_rows = nullptr;
     bool initialized = false;
     std::string err;
 };
@@ -117,15 +132,38 @@ ClassCfg choose_class(int N)
     return ClassCfg{0, 0};
 }
 
+// Chunk configuration for a grid too large for one workgroup: (4, 8), i.e.
+// 2048 points per workgroup, unless ADSCL_TUNE names another supported one.
+ClassCfg choose_big_class(int N)
+{
+    if (const char* t = std::getenv("ADSCL_TUNE")) {
+        std::string s(t);
+        size_t pos = 0;
+        while (pos < s.size()) {
+            size_t end = s.find(',', pos);
+            if (end == std::string::npos) end = s.size();
+            int n = 0, p = 0, w = 0;
+            if (std::sscanf(s.substr(pos, end - pos).c_str(), "%d:%dx%d", &n, &p, &w) == 3 && n == N) {
+                ClassCfg c{p, w};
+                if (big_class_supported(c)) return c;
+            }
+            pos = end + 1;
+        }
+    }
+    return ClassCfg{4, 8};
+}
+
 // sin, cos in long double for the tables (the kernel reads FP64 values).
-void host_tables(int N, ClassCfg cfg, std::vector<double>& tab)
+// `chunks` > 1: one [3][P][64 W] block per chunk of 64 W P points.
+void host_tables(int N, ClassCfg cfg, std::vector<double>& tab, int chunks = 1)
 {
     const int NL = 64 * cfg.W, P = cfg.P;
-    tab.assign(table_len(cfg), 0.0);
+    tab.assign(table_len(cfg) * chunks, 0.0);
     const long double h = (3.14159265358979323846264338327950288L / 2.0L) / (long double)(N - 1);
+    for (int ch = 0; ch < chunks; ++ch)
     for (int lane = 0; lane < NL; ++lane) {
         for (int k = 0; k < P; ++k) {
-            const int i = lane * P + k;
+            const int i = ch * NL * P + lane * P + k;
             double sc = 0.0, t2 = 0.0, ct2 = 0.0;
             if (i >= 1 && i <= N - 2) {
                 const long double x = h * (long double)i;
@@ -134,9 +172,10 @@ void host_tables(int N, ClassCfg cfg, std::vector<double>& tab)
                 t2 = (double)((s * s) / (c * c));
                 ct2 = (double)((c * c) / (s * s));
             }
-            tab[(size_t)(0 * P + k) * NL + lane] = sc;
-            tab[(size_t)(1 * P + k) * NL + lane] = t2;
-            tab[(size_t)(2 * P + k) * NL + lane] = ct2;
+            const size_t base = (size_t)ch * table_len(cfg);
+            tab[base + (size_t)(0 * P + k) * NL + lane] = sc;
+            tab[base + (size_t)(1 * P + k) * NL + lane] = t2;
+            tab[base + (size_t)(2 * P + k) * NL + lane] = ct2;
         }
     }
 }
@@ -191,7 +230,7 @@ void host_modes(int N, int J, std::vector<double>& e, std::vector<double>& wpi, 
 int ensure_tmp(adscl_ctx* c, size_t bytes)
 {
     if (bytes <= c->tmp_bytes) return ADSCL_OK;
-    if (c->d_tmp) hipFree(c->d_tmp);
+    if (c->d_tmp) (void)hipFree(c->d_tmp);
     c->d_tmp = nullptr;
     c->tmp_bytes = 0;
     HIP_TRY(c, hipMalloc((void**)&c->d_tmp, bytes));
@@ -260,11 +299,12 @@ int buffer(adscl_ctx* c, const char* name, size_t bytes, void** out)
 template <class F>
 int run_classes(adscl_ctx* c, F&& launch)
 {
-    hipEvent_t fork;
-    HIP_TRY(c, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    HIP_TRY(c, hipEventRecord(fork, c->stream));
+    hipEvent_t fork = c->fork;
+    const bool multi = c->classes.size() - c->n_big > 1;
+    if (multi) HIP_TRY(c, hipEventRecord(fork, c->stream));
     for (LaunchClass& lc : c->classes) {
-        hipStream_t s = c->classes.size() == 1 ? c->stream : lc.stream;
+        if (lc.chunks > 0) continue;
+        hipStream_t s = multi ? lc.stream : c->stream;
         if (s != c->stream) HIP_TRY(c, hipStreamWaitEvent(s, fork, 0));
         HIP_TRY(c, launch(lc, s));
         if (s != c->stream) {
@@ -272,7 +312,6 @@ int run_classes(adscl_ctx* c, F&& launch)
             HIP_TRY(c, hipStreamWaitEvent(c->stream, lc.done, 0));
         }
     }
-    HIP_TRY(c, hipEventDestroy(fork));
     return ADSCL_OK;
 }
 
@@ -303,15 +342,32 @@ EvolveArgs evolve_args(adscl_ctx* c, int32_t snap_every)
 
 // One segment of the fused kernel over all classes: every instance advances to
 // its target step, or to its next multiple of snap_every when that is > 0.
-int run_evolve(adscl_ctx* c, const EvolveArgs& base)
+int run_evolve(adscl_ctx* c, const EvolveArgs& base, bool timing = true)
 {
+    for (LaunchClass& lc : c->classes) {
+        if (lc.chunks == 0) continue;
+        BigArgs x;
+        x.inst = lc.inst[0];
+        x.chunks = lc.chunks;
+        x.xch = lc.xch;
+        x.ctr = lc.ctr;
+        x.err = lc.err;
+        EvolveArgs a = base;
+        a.order = nullptr;
+        if (timing && lc.t0) HIP_TRY(c, hipEventRecord(lc.t0, c->stream));
+        HIP_TRY(c, launch_evolve_big(lc.cfg, lc.chunks, a, x, c->stream));
+        if (timing && lc.t1) {
+            HIP_TRY(c, hipEventRecord(lc.t1, c->stream));
+            lc.timed = true;
+        }
+    }
     return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
         EvolveArgs a = base;
         a.order = lc.d_order;
         hipError_t e = hipSuccess;
-        if (lc.t0 && (e = hipEventRecord(lc.t0, s)) != hipSuccess) return e;
+        if (timing && lc.t0 && (e = hipEventRecord(lc.t0, s)) != hipSuccess) return e;
         if ((e = launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s)) != hipSuccess) return e;
-        if (lc.t1) {
+        if (timing && lc.t1) {
             if ((e = hipEventRecord(lc.t1, s)) != hipSuccess) return e;
             lc.timed = true;
         }
@@ -326,6 +382,47 @@ int run_finalize(adscl_ctx* c, bool final, int32_t snap_every, int32_t n_slots, 
     HIP_TRY(c, launch_finalize(c->n_inst, c->d_ic, c->d_status, c->state5, c->total, c->gauge,
                                (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0, c->thr, final, snap_every, n_slots,
                                snaps, c->stream));
+    return ADSCL_OK;
+}
+
+// Spectrum rows of `n_slots` states laid out as [slot][5][total] (Phi, Pi, A,
+// ... rows), grouped by grid size; rebuilt when n_slots changes.  Synchronises.
+int spec_rows(adscl_ctx* c, int n_slots)
+{
+    if (c->spec_slots == n_slots) return ADSCL_OK;
+    std::vector<SpecRow> rows;
+    c->spec_groups.clear();
+    for (const auto& kv : c->tables) {
+        const int N = kv.first;
+        const int first = (int)rows.size();
+        for (int sl = 0; sl < n_slots; ++sl) {
+            const int64_t base = (int64_t)sl * 5 * c->total;
+            for (int b = 0; b < c->n_inst; ++b) {
+                if (c->N[b] != N) continue;
+                rows.push_back(SpecRow{base + c->off[b], base + c->total + c->off[b], base + 2 * c->total + c->off[b],
+                                       (int64_t)sl * c->n_inst + b});
+            }
+        }
+        c->spec_groups.push_back({N, first, (int)rows.size() - first});
+    }
+    void* d;
+    int rc = buffer(c, "spec_rows", sizeof(SpecRow) * rows.size(), &d);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(d, rows.data(), sizeof(SpecRow) * rows.size(), hipMemcpyHostToDevice));
+    c->d_spec_rows = (SpecRow*)d;
+    c->spec_slots = n_slots;
+    return ADSCL_OK;
+}
+
+// Spectra of the states at `base` (the layout spec_rows was built for).
+int run_spectrum(adscl_ctx* c, const double* base, int J, double* E, double* Pihat, double* Phihat)
+{
+    for (const auto& g : c->spec_groups) {
+        const NTables& t = c->tables[g[0]];
+        HIP_TRY(c, launch_spectrum_rows(base, c->d_spec_rows + g[1], g[2], g[0], t.d_wPi, t.d_wPhi, J, E, Pihat,
+                                        Phihat, c->stream));
+    }
     return ADSCL_OK;
 }
 
@@ -356,6 +453,22 @@ int run_call(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every, 
     return run_finalize(c, true, 0, 0, nullptr);
 }
 
+// A large instance whose grid synchronisation ran out of time (reported as
+// an error; its state is then NONFINITE).  Synchronises.
+int check_big(adscl_ctx* c)
+{
+    for (const LaunchClass& lc : c->classes) {
+        if (lc.chunks == 0) continue;
+        int e = 0;
+        HIP_TRY(c, hipMemcpyAsync(&e, lc.err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (e)
+            return fail(c, ADSCL_EHIP, "instance " + std::to_string(lc.inst[0]) +
+                                           ": a grid synchronisation of its workgroups timed out");
+    }
+    return ADSCL_OK;
+}
+
 int after_init(adscl_ctx* c)
 {
     double* Phi = c->state5;
@@ -384,6 +497,210 @@ int after_init(adscl_ctx* c)
     return ADSCL_OK;
 }
 
+// ---- adjoint -------------------------------------------------------------
+
+// Device buffers and step counts of one adjoint configuration (T, K, J).
+struct AdjPlan {
+    int J = 0;
+    int64_t K = 0;
+    int64_t max_seg = 0;
+    double *ub = nullptr, *u0 = nullptr, *dummy = nullptr;
+    double *E0 = nullptr, *a0 = nullptr, *b0 = nullptr, *ET = nullptr, *aT = nullptr, *bT = nullptr;
+    double** d_ckp = nullptr;
+    double** d_segp = nullptr;
+    double** d_stgp = nullptr;
+    InstStatus* rst = nullptr;
+    AdjSeg* sgs = nullptr;
+};
+
+// Host part: step counts n_final for T, buffer sizes, per-instance pointer
+// tables, the constants upload.  Synchronises the stream.
+int adj_plan(adscl_ctx* c, double T, int64_t K, int J, AdjPlan& pl)
+{
+    const int n = c->n_inst;
+    int rc;
+    std::vector<int64_t> nf(n), ck_off(n + 1), seg_off(n + 1), stg_off(n + 1);
+    pl.J = J;
+    pl.K = K;
+    pl.max_seg = 0;
+    for (int b = 0; b < n; ++b) {
+        const double r = T / c->h_ic[b].dt - 1e-9;
+        nf[b] = (r <= 0.0) ? 0 : (int64_t)std::ceil(r);
+        const NTables& t = c->tables[c->N[b]];
+        ck_off[b + 1] = ck_off[b] + (nf[b] / K + 1) * 2 * (int64_t)c->N[b];
+        seg_off[b + 1] = seg_off[b] + (std::min<int64_t>(K, nf[b]) + 1) * 2 * (int64_t)c->N[b];
+        stg_off[b + 1] = stg_off[b] + (int64_t)adjoint_scratch_len(t.cfg);
+        pl.max_seg = std::max<int64_t>(pl.max_seg, (nf[b] + K - 1) / K);
+    }
+    void *ck, *seg, *stg, *ub, *u0, *dummy, *spec, *ptrs, *rst, *sgs;
+    const size_t nJ = (size_t)n * J;
+    if ((rc = buffer(c, "ckpt", sizeof(double) * ck_off[n], &ck))) return rc;
+    if ((rc = buffer(c, "seg", sizeof(double) * seg_off[n], &seg))) return rc;
+    if ((rc = buffer(c, "stage", sizeof(double) * stg_off[n], &stg))) return rc;
+    if ((rc = buffer(c, "ubar", sizeof(double) * 2 * c->total, &ub))) return rc;
+    if ((rc = buffer(c, "u0", sizeof(double) * 2 * c->total, &u0))) return rc;
+    if ((rc = buffer(c, "dummy", sizeof(double) * 2 * c->total, &dummy))) return rc;
+    if ((rc = buffer(c, "spec", sizeof(double) * 6 * nJ, &spec))) return rc;
+    if ((rc = buffer(c, "ptrs", sizeof(double*) * 3 * n, &ptrs))) return rc;
+    if ((rc = buffer(c, "rstatus", sizeof(InstStatus) * n, &rst))) return rc;
+    if ((rc = buffer(c, "segs", sizeof(AdjSeg) * n, &sgs))) return rc;
+    pl.ub = (double*)ub;
+    pl.u0 = (double*)u0;
+    pl.dummy = (double*)dummy;
+    pl.E0 = (double*)spec;
+    pl.a0 = pl.E0 + nJ;
+    pl.b0 = pl.a0 + nJ;
+    pl.ET = pl.b0 + nJ;
+    pl.aT = pl.ET + nJ;
+    pl.bT = pl.aT + nJ;
+    pl.d_ckp = (double**)ptrs;
+    pl.d_segp = pl.d_ckp + n;
+    pl.d_stgp = pl.d_segp + n;
+    pl.rst = (InstStatus*)rst;
+    pl.sgs = (AdjSeg*)sgs;
+    std::vector<double*> hp(3 * n);
+    for (int b = 0; b < n; ++b) {
+        hp[b] = (double*)ck + ck_off[b];
+        hp[n + b] = (double*)seg + seg_off[b];
+        hp[2 * n + b] = (double*)stg + stg_off[b];
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(ptrs, hp.data(), sizeof(double*) * 3 * n, hipMemcpyHostToDevice));
+    if ((rc = spec_rows(c, 1))) return rc;
+    return upload_ic(c, T);
+}
+
+// Device part: the whole gradient computation for data eps, c (device arrays)
+// -- initial data and its spectrum, the evolution with checkpoints, the final
+// spectrum, then the reverse sweep segment by segment and the initial map.
+// Only kernel launches, event waits and device copies: no host
+// synchronisation and no memset, so that it can be captured into a graph.
+// Instances with active[b] == 0 (when active is given) are skipped.
+int adj_enqueue(adscl_ctx* c, const AdjPlan& pl, const double* d_eps, const double* d_c, int Jc,
+                const int32_t* d_active, bool timing, double* oL, double* oG, int32_t* oV)
+{
+    const int n = c->n_inst;
+    const int J = pl.J;
+    double* s5 = c->state5;
+    int rc;
+    HIP_TRY(c, launch_init_modes(n, c->d_ic, d_eps, d_c, Jc, c->d_emode, s5, s5 + c->total, c->max_N, c->stream));
+    HIP_TRY(c, launch_pins(n, c->d_ic, s5, s5 + c->total, c->stream));
+    HIP_TRY(c, launch_reset_status(n, c->d_status, c->stream));
+    if ((rc = run_finalize(c, true, 0, 0, nullptr))) return rc;
+    if (d_active) HIP_TRY(c, launch_mask(n, c->d_status, d_active, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(pl.u0, s5, sizeof(double) * 2 * c->total, hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = run_spectrum(c, s5, J, pl.E0, pl.a0, pl.b0))) return rc;
+    HIP_TRY(c, launch_set_targets(n, c->d_ic, c->d_status, INT64_MAX / 4, c->stream));
+    {
+        EvolveArgs a = evolve_args(c, 0);
+        a.ckpt = pl.d_ckp;
+        a.ckpt_every = (int32_t)pl.K;
+        if ((rc = run_evolve(c, a, timing))) return rc;
+    }
+    if ((rc = run_finalize(c, true, 0, 0, nullptr))) return rc;
+    if ((rc = run_spectrum(c, s5, J, pl.ET, pl.aT, pl.bT))) return rc;
+
+    HIP_TRY(c, launch_fill(pl.ub, 2 * c->total, 0.0, c->stream));
+    EndArgs ea;
+    ea.ic = c->d_ic;
+    ea.order = nullptr;
+    ea.tab = c->d_tab;
+    ea.Phi = s5;
+    ea.Pi = s5 + c->total;
+    ea.wPi = c->d_wPi;
+    ea.wPhi = c->d_wPhi;
+    ea.Pihat = pl.aT;
+    ea.Phihat = pl.bT;
+    ea.E0 = pl.E0;
+    ea.ET = pl.ET;
+    ea.status = c->d_status;
+    ea.Ubar = pl.ub;
+    ea.total = c->total;
+    ea.sgn = 1.0;
+    ea.J = J;
+    ea.gauge = c->gauge;
+    auto run_end = [&]() {
+        return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
+            EndArgs e = ea;
+            e.order = lc.d_order;
+            return launch_endpoint(lc.cfg, lc.full, (int)lc.inst.size(), e, s);
+        });
+    };
+    if ((rc = run_end())) return rc;
+
+    EvolveArgs ra = evolve_args(c, 0);
+    ra.Phi = pl.dummy;
+    ra.Pi = pl.dummy + c->total;
+    ra.status = pl.rst;
+    ra.src = pl.d_ckp;
+    ra.src_every = (int32_t)pl.K;
+    ra.ckpt = pl.d_segp;
+    ra.ckpt_every = 1;
+    AdjointArgs aa;
+    aa.ic = c->d_ic;
+    aa.order = nullptr;
+    aa.tab = c->d_tab;
+    aa.seg = pl.d_segp;
+    aa.stg = pl.d_stgp;
+    aa.sg = pl.sgs;
+    aa.Ubar = pl.ub;
+    aa.total = c->total;
+    aa.gauge = c->gauge;
+    aa.pad = 0;
+    for (int64_t r = 0; r < pl.max_seg; ++r) {
+        HIP_TRY(c, launch_adj_prepare(n, c->d_ic, c->d_status, pl.K, r, pl.rst, pl.sgs, c->stream));
+        rc = run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
+            EvolveArgs e = ra;
+            e.order = lc.d_order;
+            hipError_t err = launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), e, s);
+            if (err != hipSuccess) return err;
+            AdjointArgs g = aa;
+            g.order = lc.d_order;
+            return launch_adjoint(lc.cfg, lc.full, (int)lc.inst.size(), g, s);
+        });
+        if (rc) return rc;
+    }
+    ea.Phi = pl.u0;
+    ea.Pi = pl.u0 + c->total;
+    ea.Pihat = pl.a0;
+    ea.Phihat = pl.b0;
+    ea.sgn = -1.0;
+    if ((rc = run_end())) return rc;
+    HIP_TRY(c, launch_adj_finish(n, c->d_ic, c->d_status, pl.ub, c->total, c->d_emode, d_eps, Jc, pl.E0, pl.ET, J,
+                                 oL, oG, oV, c->stream));
+    return ADSCL_OK;
+}
+
+int check_adjoint_args(adscl_ctx* c, const double* eps, const double* coef, int32_t Jc, int32_t J, double T,
+                       int32_t ckpt_every, int mem)
+{
+    if (!eps || !coef) return fail(c, ADSCL_EINVAL, "NULL argument");
+    if (c->flags & ADSCL_FROZEN_METRIC) return fail(c, ADSCL_EUNSUPPORTED, "adjoint needs the dynamic metric");
+    if (c->n_big > 0) return fail(c, ADSCL_EUNSUPPORTED, "adjoint supports N <= 4097");
+    if (Jc < 1 || Jc > c->n_modes || J < 1 || J > c->n_modes)
+        return fail(c, ADSCL_EINVAL, "need 1 <= Jc, J <= n_modes");
+    if (!(T >= 0.0) || std::isinf(T)) return fail(c, ADSCL_EINVAL, "T must be finite and >= 0");
+    if (ckpt_every < 1) return fail(c, ADSCL_EINVAL, "ckpt_every must be >= 1");
+    return check_mem(c, mem);
+}
+
+// Device copies of eps [n] and c [n x Jc] in context buffers.
+int stage_inputs(adscl_ctx* c, const double* eps, const double* coef, int32_t Jc, int mem, double** d_eps,
+                 double** d_c)
+{
+    void *e, *k;
+    int rc;
+    const int n = c->n_inst;
+    if ((rc = buffer(c, "in_eps", sizeof(double) * n, &e))) return rc;
+    if ((rc = buffer(c, "in_c", sizeof(double) * (size_t)n * Jc, &k))) return rc;
+    const hipMemcpyKind kind = mem == ADSCL_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(c, hipMemcpyAsync(e, eps, sizeof(double) * n, kind, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(k, coef, sizeof(double) * (size_t)n * Jc, kind, c->stream));
+    *d_eps = (double*)e;
+    *d_c = (double*)k;
+    return ADSCL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,10 +713,10 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     if (cfg->n_inst < 1) return fail(nullptr, ADSCL_EINVAL, "n_inst must be >= 1");
     for (int b = 0; b < cfg->n_inst; ++b) {
         const int N = cfg->n_grid[b];
-        if (N < 17 || N > 4097 || (N % 2) == 0)
+        if (N < 17 || N > kMaxN || (N % 2) == 0)
             return fail(nullptr, ADSCL_EINVAL,
                         "instance " + std::to_string(b) + ": N=" + std::to_string(N) +
-                            " (need odd N, 17 <= N <= 4097)");
+                            " (need odd N, 17 <= N <= 65537)");
     }
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return fail(nullptr, ADSCL_EINVAL, "cfl must be in (0, 1]");
     if (!(cfg->ko_sigma >= 0.0 && cfg->ko_sigma <= 2.0)) return fail(nullptr, ADSCL_EINVAL, "ko_sigma must be in [0, 2]");
@@ -470,6 +787,55 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     std::map<std::pair<int, int>, std::map<bool, int>> class_index;
     for (int b = 0; b < c->n_inst; ++b) {
         const int N = c->N[b];
+        if (N > kMaxOneGroup) {
+            // a large instance: chunks of one class over several workgroups
+            int coop = 0;
+            TRY_C(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+            if (!coop) {
+                c->err = "N=" + std::to_string(N) + " needs cooperative launches";
+                return bail(ADSCL_EUNSUPPORTED);
+            }
+            const ClassCfg cfg = choose_big_class(N);
+            const int C = 64 * cfg.W * cfg.P;
+            const int G = (N - 1 + C - 1) / C;
+            const int rem = (N - 1) - (G - 1) * C;
+            if (G > kBigMaxChunks || rem < 8 || big_lds_bytes(cfg) > c->max_lds) {
+                c->err = "N=" + std::to_string(N) + ": no chunk configuration (chunks of " + std::to_string(C) +
+                         " points leave " + std::to_string(rem) + " in the last)";
+                return bail(ADSCL_EUNSUPPORTED);
+            }
+            if (!c->tables.count(N)) {
+                NTables t;
+                t.cfg = cfg;
+                TRY_C(prepare_evolve_big(cfg, c->max_lds));
+                std::vector<double> tab, e, wpi, wphi;
+                host_tables(N, cfg, tab, G);
+                TRY_C(hipMalloc((void**)&t.d_tab, tab.size() * sizeof(double)));
+                TRY_C(hipMemcpy(t.d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+                if (c->n_modes > 0) {
+                    host_modes(N, c->n_modes, e, wpi, wphi);
+                    const size_t bytes = e.size() * sizeof(double);
+                    TRY_C(hipMalloc((void**)&t.d_emode, bytes));
+                    TRY_C(hipMalloc((void**)&t.d_wPi, bytes));
+                    TRY_C(hipMalloc((void**)&t.d_wPhi, bytes));
+                    TRY_C(hipMemcpy(t.d_emode, e.data(), bytes, hipMemcpyHostToDevice));
+                    TRY_C(hipMemcpy(t.d_wPi, wpi.data(), bytes, hipMemcpyHostToDevice));
+                    TRY_C(hipMemcpy(t.d_wPhi, wphi.data(), bytes, hipMemcpyHostToDevice));
+                }
+                c->tables[N] = t;
+            }
+            LaunchClass lc;
+            lc.cfg = cfg;
+            lc.full = false;
+            lc.chunks = G;
+            lc.inst.push_back(b);
+            TRY_C(hipMalloc((void**)&lc.xch, sizeof(double) * 32 * (size_t)G));
+            TRY_C(hipMalloc((void**)&lc.ctr, sizeof(unsigned long long) * 2));
+            lc.err = (int*)(lc.ctr + 1);
+            TRY_C(hipMemset(lc.ctr, 0, sizeof(unsigned long long) * 2));
+            c->classes.push_back(lc);
+            continue;
+        }
         if (!c->tables.count(N)) {
             NTables t;
             t.cfg = choose_class(N);
@@ -517,7 +883,7 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
         std::stable_sort(lc.inst.begin(), lc.inst.end(), [&](int x, int y) { return c->N[x] > c->N[y]; });
         TRY_C(hipMalloc((void**)&lc.d_order, lc.inst.size() * sizeof(int32_t)));
         TRY_C(hipMemcpy(lc.d_order, lc.inst.data(), lc.inst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        if (c->classes.size() > 1) {
+        if (c->classes.size() > 1 && lc.chunks == 0) {
             TRY_C(hipStreamCreateWithFlags(&lc.stream, hipStreamNonBlocking));
             TRY_C(hipEventCreateWithFlags(&lc.done, hipEventDisableTiming));
         }
@@ -526,10 +892,15 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
             TRY_C(hipEventCreate(&lc.t1));
         }
     }
-    // launch the biggest classes first
+    if (c->classes.size() > 1) TRY_C(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    // launch the biggest classes first (large instances last: they run after
+    // the others, on the context stream)
     std::stable_sort(c->classes.begin(), c->classes.end(), [](const LaunchClass& x, const LaunchClass& y) {
+        if ((x.chunks > 0) != (y.chunks > 0)) return y.chunks > 0;
         return 64 * x.cfg.W * x.cfg.P > 64 * y.cfg.W * y.cfg.P;
     });
+    c->n_big = 0;
+    for (const LaunchClass& lc : c->classes) c->n_big += lc.chunks > 0;
 
     std::vector<const double*> tabp(c->n_inst), ep(c->n_inst), wpp(c->n_inst), wfp(c->n_inst);
     for (int b = 0; b < c->n_inst; ++b) {
@@ -565,31 +936,34 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
 void adscl_destroy(adscl_ctx* c)
 {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (LaunchClass& lc : c->classes) {
-        if (lc.d_order) hipFree(lc.d_order);
-        if (lc.stream) hipStreamDestroy(lc.stream);
-        if (lc.done) hipEventDestroy(lc.done);
-        if (lc.t0) hipEventDestroy(lc.t0);
-        if (lc.t1) hipEventDestroy(lc.t1);
+        if (lc.xch) (void)hipFree(lc.xch);
+        if (lc.ctr) (void)hipFree(lc.ctr);
+        if (lc.d_order) (void)hipFree(lc.d_order);
+        if (lc.stream) (void)hipStreamDestroy(lc.stream);
+        if (lc.done) (void)hipEventDestroy(lc.done);
+        if (lc.t0) (void)hipEventDestroy(lc.t0);
+        if (lc.t1) (void)hipEventDestroy(lc.t1);
     }
     for (auto& kv : c->tables) {
-        if (kv.second.d_tab) hipFree(kv.second.d_tab);
-        if (kv.second.d_emode) hipFree(kv.second.d_emode);
-        if (kv.second.d_wPi) hipFree(kv.second.d_wPi);
-        if (kv.second.d_wPhi) hipFree(kv.second.d_wPhi);
+        if (kv.second.d_tab) (void)hipFree(kv.second.d_tab);
+        if (kv.second.d_emode) (void)hipFree(kv.second.d_emode);
+        if (kv.second.d_wPi) (void)hipFree(kv.second.d_wPi);
+        if (kv.second.d_wPhi) (void)hipFree(kv.second.d_wPhi);
     }
-    if (c->d_tab) hipFree((void*)c->d_tab);
-    if (c->d_emode) hipFree((void*)c->d_emode);
-    if (c->d_wPi) hipFree((void*)c->d_wPi);
-    if (c->d_wPhi) hipFree((void*)c->d_wPhi);
-    if (c->state5) hipFree(c->state5);
-    if (c->d_status) hipFree(c->d_status);
-    if (c->d_ic) hipFree(c->d_ic);
-    if (c->d_tmp) hipFree(c->d_tmp);
+    if (c->d_tab) (void)hipFree((void*)c->d_tab);
+    if (c->d_emode) (void)hipFree((void*)c->d_emode);
+    if (c->d_wPi) (void)hipFree((void*)c->d_wPi);
+    if (c->d_wPhi) (void)hipFree((void*)c->d_wPhi);
+    if (c->state5) (void)hipFree(c->state5);
+    if (c->d_status) (void)hipFree(c->d_status);
+    if (c->d_ic) (void)hipFree(c->d_ic);
+    if (c->d_tmp) (void)hipFree(c->d_tmp);
+    if (c->fork) (void)hipEventDestroy(c->fork);
     for (auto& kv : c->bufs)
-        if (kv.second.first) hipFree(kv.second.first);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+        if (kv.second.first) (void)hipFree(kv.second.first);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -655,13 +1029,14 @@ int adscl_step(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every
         }
     }
     int rc = run_call(c, max_steps, t_end, want ? snap_every : 0, want ? n_snap_slots : 0, dsn);
+    if (rc == ADSCL_OK && c->n_big > 0) rc = check_big(c);
     if (want && mem == ADSCL_MEM_HOST) {
         if (rc == ADSCL_OK) {
             hipError_t e = hipMemcpyAsync(snaps, dsn, snap_bytes, hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
             if (e != hipSuccess) rc = fail(c, ADSCL_EHIP, std::string("snapshot copy: ") + hipGetErrorString(e));
         }
-        hipFree(dsn);
+        (void)hipFree(dsn);
     }
     return rc;
 }
@@ -715,26 +1090,23 @@ int adscl_constraints(adscl_ctx* c, double* out, int mem)
     return ADSCL_OK;
 }
 
-int adscl_spectrum(adscl_ctx* c, int32_t J, double* E, double* Pihat, double* Phihat, int mem)
+// Spectra of n_slots states at `base` ([slot][5][total] on the device) into
+// E, Pihat, Phihat ([n_slots][n_inst][J], host or device per mem).
+static int spectrum_call(adscl_ctx* c, const double* base, int n_slots, int32_t J, double* E, double* Pihat, double* Phihat,
+                  int mem)
 {
-    if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
-    if (!c->initialized) return fail(c, ADSCL_ESTATE, "adscl_spectrum before any adscl_init*");
-    if (J < 1 || J > c->n_modes) return fail(c, ADSCL_EINVAL, "need 1 <= J <= n_modes");
-    if (int rc = check_mem(c, mem)) return rc;
-    const size_t n = (size_t)c->n_inst * J;
+    int rc;
+    if ((rc = spec_rows(c, n_slots))) return rc;
+    const size_t n = (size_t)n_slots * c->n_inst * J;
     double *dE = E, *dP = Pihat, *dF = Phihat;
     if (mem == ADSCL_MEM_HOST) {
-        dE = E ? c->d_tmp : nullptr;
-        dP = Pihat ? c->d_tmp + n : nullptr;
-        dF = Phihat ? c->d_tmp + 2 * n : nullptr;
-        if (int rc = ensure_tmp(c, 3 * n * sizeof(double))) return rc;
-        dE = E ? c->d_tmp : nullptr;
-        dP = Pihat ? c->d_tmp + n : nullptr;
-        dF = Phihat ? c->d_tmp + 2 * n : nullptr;
+        void* t;
+        if ((rc = buffer(c, "spec_out", 3 * n * sizeof(double), &t))) return rc;
+        dE = E ? (double*)t : nullptr;
+        dP = Pihat ? (double*)t + n : nullptr;
+        dF = Phihat ? (double*)t + 2 * n : nullptr;
     }
-    const double* s = c->state5;
-    HIP_TRY(c, launch_spectrum(c->n_inst, c->d_ic, s, s + c->total, s + 2 * c->total, c->d_wPi, c->d_wPhi, J, dE,
-                               dP, dF, c->stream));
+    if ((rc = run_spectrum(c, base, J, dE, dP, dF))) return rc;
     if (mem == ADSCL_MEM_HOST) {
         if (E) HIP_TRY(c, hipMemcpyAsync(E, dE, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         if (Pihat) HIP_TRY(c, hipMemcpyAsync(Pihat, dP, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -744,157 +1116,47 @@ int adscl_spectrum(adscl_ctx* c, int32_t J, double* E, double* Pihat, double* Ph
     return ADSCL_OK;
 }
 
+int adscl_spectrum(adscl_ctx* c, int32_t J, double* E, double* Pihat, double* Phihat, int mem)
+{
+    if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
+    if (!c->initialized) return fail(c, ADSCL_ESTATE, "adscl_spectrum before any adscl_init*");
+    if (J < 1 || J > c->n_modes) return fail(c, ADSCL_EINVAL, "need 1 <= J <= n_modes");
+    if (int rc = check_mem(c, mem)) return rc;
+    return spectrum_call(c, c->state5, 1, J, E, Pihat, Phihat, mem);
+}
+
+int adscl_spectrum_snaps(adscl_ctx* c, int32_t J, int32_t n_slots, const double* snaps, double* E, double* Pihat,
+                         double* Phihat, int mem)
+{
+    if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
+    if (J < 1 || J > c->n_modes) return fail(c, ADSCL_EINVAL, "need 1 <= J <= n_modes");
+    if (n_slots < 1 || !snaps) return fail(c, ADSCL_EINVAL, "need n_slots >= 1 and snaps");
+    if (int rc = check_mem(c, mem)) return rc;
+    const double* base = snaps;
+    if (mem == ADSCL_MEM_HOST) {
+        void* t;
+        const size_t bytes = sizeof(double) * 5 * (size_t)c->total * n_slots;
+        if (int rc = buffer(c, "snaps_in", bytes, &t)) return rc;
+        HIP_TRY(c, hipMemcpyAsync(t, snaps, bytes, hipMemcpyHostToDevice, c->stream));
+        base = (const double*)t;
+    }
+    return spectrum_call(c, base, n_slots, J, E, Pihat, Phihat, mem);
+}
+
 int adscl_adjoint(adscl_ctx* c, const double* eps, const double* coef, int32_t Jc, int32_t J, double T,
                   int32_t ckpt_every, double* L, double* dLdc, int32_t* valid, int mem)
 {
     if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
-    if (!eps || !coef || !L || !dLdc || !valid) return fail(c, ADSCL_EINVAL, "NULL argument");
-    if (c->flags & ADSCL_FROZEN_METRIC) return fail(c, ADSCL_EUNSUPPORTED, "adjoint needs the dynamic metric");
-    if (Jc < 1 || Jc > c->n_modes || J < 1 || J > c->n_modes)
-        return fail(c, ADSCL_EINVAL, "need 1 <= Jc, J <= n_modes");
-    if (!(T >= 0.0) || std::isinf(T)) return fail(c, ADSCL_EINVAL, "T must be finite and >= 0");
-    if (ckpt_every < 1) return fail(c, ADSCL_EINVAL, "ckpt_every must be >= 1");
-    if (int rc = check_mem(c, mem)) return rc;
+    if (!L || !dLdc || !valid) return fail(c, ADSCL_EINVAL, "NULL output");
+    int rc = check_adjoint_args(c, eps, coef, Jc, J, T, ckpt_every, mem);
+    if (rc) return rc;
     const int n = c->n_inst;
-    const int64_t K = ckpt_every;
-    int rc;
-
-    // per-instance step counts and buffer sizes (doubles)
-    std::vector<int64_t> nf(n), ck_off(n + 1), seg_off(n + 1), stg_off(n + 1);
-    for (int b = 0; b < n; ++b) {
-        const double r = T / c->h_ic[b].dt - 1e-9;
-        nf[b] = (r <= 0.0) ? 0 : (int64_t)std::ceil(r);
-        const NTables& t = c->tables[c->N[b]];
-        ck_off[b + 1] = ck_off[b] + (nf[b] / K + 1) * 2 * (int64_t)c->N[b];
-        seg_off[b + 1] = seg_off[b] + (std::min<int64_t>(K, nf[b]) + 1) * 2 * (int64_t)c->N[b];
-        stg_off[b + 1] = stg_off[b] + (int64_t)adjoint_scratch_len(t.cfg);
-    }
-    void *ck, *seg, *stg, *ub, *u0, *dummy, *spec, *deps, *ptrs, *rst, *sgs, *outs;
-    const size_t nJ = (size_t)n * J;
-    if ((rc = buffer(c, "ckpt", sizeof(double) * ck_off[n], &ck))) return rc;
-    if ((rc = buffer(c, "seg", sizeof(double) * seg_off[n], &seg))) return rc;
-    if ((rc = buffer(c, "stage", sizeof(double) * stg_off[n], &stg))) return rc;
-    if ((rc = buffer(c, "ubar", sizeof(double) * 2 * c->total, &ub))) return rc;
-    if ((rc = buffer(c, "u0", sizeof(double) * 2 * c->total, &u0))) return rc;
-    if ((rc = buffer(c, "dummy", sizeof(double) * 2 * c->total, &dummy))) return rc;
-    if ((rc = buffer(c, "spec", sizeof(double) * 6 * nJ, &spec))) return rc;
-    if ((rc = buffer(c, "eps", sizeof(double) * n, &deps))) return rc;
-    if ((rc = buffer(c, "ptrs", sizeof(double*) * 3 * n, &ptrs))) return rc;
-    if ((rc = buffer(c, "rstatus", sizeof(InstStatus) * n, &rst))) return rc;
-    if ((rc = buffer(c, "segs", sizeof(AdjSeg) * n, &sgs))) return rc;
+    double *d_eps, *d_c;
+    if ((rc = stage_inputs(c, eps, coef, Jc, mem, &d_eps, &d_c))) return rc;
+    AdjPlan pl;
+    if ((rc = adj_plan(c, T, ckpt_every, J, pl))) return rc;
+    void* outs;
     if ((rc = buffer(c, "outs", sizeof(double) * ((size_t)n * Jc + 2 * n), &outs))) return rc;
-    double* E0 = (double*)spec;
-    double* a0 = E0 + nJ;
-    double* b0 = a0 + nJ;
-    double* ET = b0 + nJ;
-    double* aT = ET + nJ;
-    double* bT = aT + nJ;
-    double** d_ckp = (double**)ptrs;
-    double** d_segp = d_ckp + n;
-    double** d_stgp = d_segp + n;
-    {
-        std::vector<double*> hp(3 * n);
-        for (int b = 0; b < n; ++b) {
-            hp[b] = (double*)ck + ck_off[b];
-            hp[n + b] = (double*)seg + seg_off[b];
-            hp[2 * n + b] = (double*)stg + stg_off[b];
-        }
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        HIP_TRY(c, hipMemcpy(ptrs, hp.data(), sizeof(double*) * 3 * n, hipMemcpyHostToDevice));
-    }
-    HIP_TRY(c, hipMemcpyAsync(deps, eps, sizeof(double) * n,
-                              mem == ADSCL_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-
-    // forward: initial data, its spectrum, the evolution with checkpoints, the
-    // final spectrum
-    if ((rc = adscl_init_modes(c, eps, coef, Jc, mem))) return rc;
-    const double* s5 = c->state5;
-    HIP_TRY(c, hipMemcpyAsync(u0, s5, sizeof(double) * 2 * c->total, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, launch_spectrum(n, c->d_ic, s5, s5 + c->total, s5 + 2 * c->total, c->d_wPi, c->d_wPhi, J, E0, a0, b0,
-                               c->stream));
-    if ((rc = upload_ic(c, T))) return rc;
-    HIP_TRY(c, launch_set_targets(n, c->d_ic, c->d_status, INT64_MAX / 4, c->stream));
-    {
-        EvolveArgs a = evolve_args(c, 0);
-        a.ckpt = d_ckp;
-        a.ckpt_every = (int32_t)K;
-        if ((rc = run_evolve(c, a))) return rc;
-    }
-    if ((rc = run_finalize(c, true, 0, 0, nullptr))) return rc;
-    HIP_TRY(c, launch_spectrum(n, c->d_ic, s5, s5 + c->total, s5 + 2 * c->total, c->d_wPi, c->d_wPhi, J, ET, aT, bT,
-                               c->stream));
-
-    // reverse: final spectrum, segments from the last to the first, initial
-    // spectrum, initial map
-    HIP_TRY(c, hipMemsetAsync(ub, 0, sizeof(double) * 2 * c->total, c->stream));
-    EndArgs ea;
-    ea.ic = c->d_ic;
-    ea.order = nullptr;
-    ea.tab = c->d_tab;
-    ea.Phi = s5;
-    ea.Pi = s5 + c->total;
-    ea.wPi = c->d_wPi;
-    ea.wPhi = c->d_wPhi;
-    ea.Pihat = aT;
-    ea.Phihat = bT;
-    ea.E0 = E0;
-    ea.ET = ET;
-    ea.status = c->d_status;
-    ea.Ubar = (double*)ub;
-    ea.total = c->total;
-    ea.sgn = 1.0;
-    ea.J = J;
-    ea.gauge = c->gauge;
-    auto run_end = [&]() {
-        return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
-            EndArgs e = ea;
-            e.order = lc.d_order;
-            return launch_endpoint(lc.cfg, lc.full, (int)lc.inst.size(), e, s);
-        });
-    };
-    if ((rc = run_end())) return rc;
-
-    int64_t max_seg = 0;
-    for (int b = 0; b < n; ++b) max_seg = std::max<int64_t>(max_seg, (nf[b] + K - 1) / K);
-    EvolveArgs ra = evolve_args(c, 0);
-    ra.Phi = (double*)dummy;
-    ra.Pi = (double*)dummy + c->total;
-    ra.status = (InstStatus*)rst;
-    ra.src = d_ckp;
-    ra.src_every = (int32_t)K;
-    ra.ckpt = d_segp;
-    ra.ckpt_every = 1;
-    AdjointArgs aa;
-    aa.ic = c->d_ic;
-    aa.order = nullptr;
-    aa.tab = c->d_tab;
-    aa.seg = d_segp;
-    aa.stg = d_stgp;
-    aa.sg = (AdjSeg*)sgs;
-    aa.Ubar = (double*)ub;
-    aa.total = c->total;
-    aa.gauge = c->gauge;
-    aa.pad = 0;
-    for (int64_t r = 0; r < max_seg; ++r) {
-        HIP_TRY(c, launch_adj_prepare(n, c->d_ic, c->d_status, K, r, (InstStatus*)rst, (AdjSeg*)sgs, c->stream));
-        rc = run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
-            EvolveArgs e = ra;
-            e.order = lc.d_order;
-            hipError_t err = launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), e, s);
-            if (err != hipSuccess) return err;
-            AdjointArgs g = aa;
-            g.order = lc.d_order;
-            return launch_adjoint(lc.cfg, lc.full, (int)lc.inst.size(), g, s);
-        });
-        if (rc) return rc;
-    }
-    ea.Phi = (const double*)u0;
-    ea.Pi = (const double*)u0 + c->total;
-    ea.Pihat = a0;
-    ea.Phihat = b0;
-    ea.sgn = -1.0;
-    if ((rc = run_end())) return rc;
-
     double* oL = (double*)outs;
     double* oG = oL + n;
     int32_t* oV = (int32_t*)(oG + (size_t)n * Jc);
@@ -903,14 +1165,87 @@ int adscl_adjoint(adscl_ctx* c, const double* eps, const double* coef, int32_t J
         oG = dLdc;
         oV = valid;
     }
-    HIP_TRY(c, launch_adj_finish(n, c->d_ic, c->d_status, (const double*)ub, c->total, c->d_emode,
-                                 (const double*)deps, Jc, E0, ET, J, oL, oG, oV, c->stream));
+    if ((rc = adj_enqueue(c, pl, d_eps, d_c, Jc, nullptr, true, oL, oG, oV))) return rc;
+    c->initialized = true;
     if (mem == ADSCL_MEM_HOST) {
         HIP_TRY(c, hipMemcpyAsync(L, oL, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipMemcpyAsync(dLdc, oG, sizeof(double) * n * Jc, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipMemcpyAsync(valid, oV, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
+    return ADSCL_OK;
+}
+
+int adscl_descend(adscl_ctx* c, const double* eps, double* coef, int32_t Jc, int32_t J, double T,
+                  int32_t ckpt_every, int32_t iters, double step0, int32_t flags, double* L_hist, int32_t* active,
+                  int mem)
+{
+    if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
+    if (!L_hist || !active) return fail(c, ADSCL_EINVAL, "NULL output");
+    int rc = check_adjoint_args(c, eps, coef, Jc, J, T, ckpt_every, mem);
+    if (rc) return rc;
+    if (iters < 1) return fail(c, ADSCL_EINVAL, "iters must be >= 1");
+    if (!(step0 > 0.0) || std::isinf(step0)) return fail(c, ADSCL_EINVAL, "step0 must be finite and > 0");
+    if (flags & ~ADSCL_DESCEND_EAGER) return fail(c, ADSCL_EINVAL, "unknown flags");
+    const int n = c->n_inst;
+    double *d_eps, *d_c;
+    if ((rc = stage_inputs(c, eps, coef, Jc, mem, &d_eps, &d_c))) return rc;
+    AdjPlan pl;
+    if ((rc = adj_plan(c, T, ckpt_every, J, pl))) return rc;
+    void *g, *lv, *vv, *st, *act, *it, *hist;
+    if ((rc = buffer(c, "gd_grad", sizeof(double) * (size_t)n * Jc, &g))) return rc;
+    if ((rc = buffer(c, "gd_L", sizeof(double) * n, &lv))) return rc;
+    if ((rc = buffer(c, "gd_valid", sizeof(int32_t) * n, &vv))) return rc;
+    if ((rc = buffer(c, "gd_state", sizeof(double) * 2 * n, &st))) return rc;
+    if ((rc = buffer(c, "gd_active", sizeof(int32_t) * n, &act))) return rc;
+    if ((rc = buffer(c, "gd_iter", sizeof(int32_t), &it))) return rc;
+    if ((rc = buffer(c, "gd_hist", sizeof(double) * (size_t)iters * n, &hist))) return rc;
+    GdState gs;
+    gs.s = (double*)st;
+    gs.Lprev = (double*)st + n;
+    gs.active = (int32_t*)act;
+    gs.iter = (int32_t*)it;
+    HIP_TRY(c, launch_gd_init(n, step0, gs, c->stream));
+    auto one_iteration = [&](bool timing) -> int {
+        int r = adj_enqueue(c, pl, d_eps, d_c, Jc, gs.active, timing, (double*)lv, (double*)g, (int32_t*)vv);
+        if (r) return r;
+        HIP_TRY(c, launch_gd_update(n, Jc, d_c, (const double*)g, (const double*)lv, (const int32_t*)vv, gs,
+                                    (double*)hist, c->stream));
+        return ADSCL_OK;
+    };
+    if (flags & ADSCL_DESCEND_EAGER) {
+        for (int i = 0; i < iters; ++i)
+            if ((rc = one_iteration(true))) return rc;
+    } else {
+        // one iteration captured once, replayed `iters` times
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        rc = one_iteration(false);
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(c, ADSCL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(c, ADSCL_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        for (int i = 0; i < iters && e == hipSuccess; ++i) e = hipGraphLaunch(exec, c->stream);
+        hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(c, ADSCL_EHIP, std::string("graph launch: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    c->initialized = true;
+    const hipMemcpyKind kind = mem == ADSCL_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(c, hipMemcpyAsync(coef, d_c, sizeof(double) * (size_t)n * Jc, kind, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(L_hist, hist, sizeof(double) * (size_t)iters * n, kind, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(active, act, sizeof(int32_t) * n, kind, c->stream));
+    if (mem == ADSCL_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
     return ADSCL_OK;
 }
 

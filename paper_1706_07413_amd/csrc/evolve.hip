@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     const int N = sg.N, i0 = sg.i0;
     const double dt = sg.dt;
 
-    double un0[P], un1[P], acc0[P], acc1[P];
+    double un0[P], un1[P], acc0[P], acc1[P], cv0[P], cv1[P];  // cv: the current stage input
     const ADSCL_GLOBAL double* s0 = gmem(a.Phi + off);
     const ADSCL_GLOBAL double* s1 = gmem(a.Pi + off);
     if (a.src) {
@@ -61,6 +61,8 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
         un1[k] = o ? s1[j] : 0.0;
         acc0[k] = 0.0;
         acc1[k] = 0.0;
+        cv0[k] = un0[k];
+        cv1[k] = un1[k];
     }
 
     // One RK4 stage on the published stage input; returns true when stage 0
@@ -68,14 +70,13 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     int stop_bits = 0;
     auto stage = [&](const int s) -> bool {
         double r0[P], r1[P];
-        const int bits = sg.rhs(s == 0, frozen, r0, r1);
+        const int bits = sg.rhs(s == 0, frozen, cv0, cv1, r0, r1);
         if (bits) {
             stop_bits = bits;
             return true;
         }
         const double c_next = (s == 2) ? dt : 0.5 * dt;
         const double wacc = (s == 0 || s == 3) ? 1.0 : 2.0;
-        double us0[P], us1[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             if (s == 0) {
@@ -86,17 +87,17 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
                 acc1[k] = acc1[k] + wacc * r1[k];
             }
             if (s < 3) {
-                us0[k] = un0[k] + c_next * r0[k];
-                us1[k] = un1[k] + c_next * r1[k];
+                cv0[k] = un0[k] + c_next * r0[k];
+                cv1[k] = un1[k] + c_next * r1[k];
             } else {
                 un0[k] = un0[k] + (dt / 6.0) * acc0[k];
                 un1[k] = un1[k] + (dt / 6.0) * acc1[k];
-                us0[k] = un0[k];
-                us1[k] = un1[k];
+                cv0[k] = un0[k];
+                cv1[k] = un1[k];
             }
         }
         // every lane read U_s before B3, so U_{s+1} may replace it now
-        sg.publish(us0, us1);
+        sg.publish(cv0, cv1);
         return false;
     };
 
@@ -212,7 +213,8 @@ bool class_supported(ClassCfg c)
 
 size_t evolve_lds_bytes(ClassCfg c)
 {
-    return (size_t)(4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8) * sizeof(double);
+    return (size_t)(4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + (c.P >= 8 ? 2 * 64 * c.W : 0)) *
+           sizeof(double);
 }
 
 hipError_t prepare_evolve(ClassCfg c, size_t max_lds)

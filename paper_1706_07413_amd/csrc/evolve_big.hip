@@ -1,0 +1,640 @@
+// RK4 evolution of one large instance (N above what one workgroup holds) over
+// several workgroups, gfx950 (Liebling & Khanna, arXiv:1706.07413, Sec. II).
+//
+// The instance's evolved points are cut into G chunks of C = 64 W P points; the
+// workgroup of chunk g keeps its points on chip exactly as the single-workgroup
+// kernel does (lane-interleaved LDS rows, state in registers) and exchanges
+// with the other workgroups through a small global record per chunk, behind
+// three grid-wide synchronisations per stage:
+//   A  stage input: each chunk's first and last three points (the +-3 stencil
+//      halo of its neighbours);
+//   B  the constraint scans.  Within a chunk both prefix sums are taken
+//      locally, the first without its carry: with R'_k the local prefix of
+//      p = sin x cos x q, delta~'_k = -h/24 (24 R'_k - 12 p_k + p_{k-1} - p_{k+1})
+//      and E'_k = exp(-delta~'_k), the true weight is e^{-(delta~_k - shift)} =
+//      E'_k F_g with one factor per chunk, F_g = exp(24 h/24 C_g + 2 h/24 p_1 +
+//      shift), C_g the p total of the chunks before g.  So the local prefix
+//      sums of p and of sigma' = tan^2 x q E'_k are all a chunk publishes
+//      (with its edge values), and every chunk then finishes its own points:
+//      S_k = h/24 (24 (D_g + F_g R2'_k) - 12 s_k + s_{k-1} - s_{k+1}), s = F sigma',
+//      D_g = sum_{h<g} F_h (sigma' total of h);
+//   C  fluxes: each chunk's first and last two (f1, g) values, and the
+//      collapse / non-finite bits of the step's first stage.
+// The synchronisation is a monotonic 64-bit arrival counter per instance:
+// every workgroup adds one and waits, with a bounded spin, until all G have
+// arrived; a spin that runs out sets an error flag and every workgroup leaves
+// (the host reports it).  The launch is cooperative, so all G workgroups are
+// resident together.
+#include <math.h>
+
+#include "stage.h"
+
+namespace adscl {
+namespace {
+
+// Per-chunk exchange record (doubles).
+enum : int {
+    XU_L = 0,    // (Phi, Pi) of points a, a+1, a+2
+    XU_R = 6,    // (Phi, Pi) of points a+C-1, a+C-2, a+C-3
+    XS_P = 12,   // p total of the chunk
+    XS_S = 13,   // sigma' total of the chunk
+    XS_SF = 14,  // sigma' at the first point
+    XS_SL = 15,  // sigma' at the last point
+    XS_P1 = 16,  // p_1 (chunk 0)
+    XS_PN = 17,  // p_{N-2} (last chunk)
+    XF_L = 18,   // (f1, g) of points a, a+1
+    XF_R = 22,   // (f1, g) of points a+C-1, a+C-2
+    XF_B = 26,   // collapse / non-finite bits of the chunk
+    XREC = 32
+};
+
+constexpr unsigned long long kSpinLimit = 1ull << 22;  // about seconds: legitimate waits are microseconds
+
+template <int P, int W>
+struct Chunk {
+    static constexpr int NL = 64 * W;
+    static constexpr int RS = NL + 2;
+    static constexpr int SLOTS = P * RS;
+    static constexpr int C = P * NL;
+    static_assert(P >= 4, "a lane must own at least 4 points");
+
+    double2* U;
+    double2* F;
+    double* PE;
+    double* SE;
+    double* red;   // as the single-workgroup kernel, plus [4W+8, 4W+8+3G) per-chunk factors
+    int tid, lane, wv, g, G, a, i0, col, N;
+    bool first, last, has_nm2, near_end, bgauge;
+    double h24, i12h, kof, thr;
+    const ADSCL_GLOBAL double* tabI;  // tables of the whole instance, [g][3][P][NL]
+    const ADSCL_GLOBAL double* tab0;  // this chunk's
+    double* xg;                        // exchange records [G][XREC]
+    unsigned long long* ctr;
+    int* err;
+    unsigned long long target;
+
+    __device__ __forceinline__ bool own(int k) const { return i0 + k <= N - 2; }
+    __device__ __forceinline__ int slot(int j) const
+    {
+        const int jl = j - a;
+        const int l = (jl >= 0) ? (jl / P) : -1 - ((-1 - jl) / P);
+        return (jl - l * P) * RS + l + 1;
+    }
+    struct TabView {
+        const ADSCL_GLOBAL char* base;
+        unsigned o;
+    };
+    __device__ __forceinline__ TabView tables() const
+    {
+        unsigned o = (unsigned)tid * 8u;
+        asm volatile("" : "+v"(o));
+        return TabView{(const ADSCL_GLOBAL char*)tab0, o};
+    }
+    __device__ __forceinline__ double tab(const TabView& v, int t, int k) const
+    {
+        return *(const ADSCL_GLOBAL double*)(v.base + (v.o + (unsigned)((t * P + k) * NL * 8)));
+    }
+    // table t at global point j of any chunk
+    __device__ __forceinline__ double tab_at(int t, int j) const
+    {
+        const int gg = j / C, jl = j - gg * C, l = jl / P, k = jl - l * P;
+        return tabI[(size_t)gg * 3 * C + (size_t)(t * P + k) * NL + l];
+    }
+
+    // Grid-wide barrier over the instance's G workgroups.  Returns false when
+    // the wait ran out (or another workgroup's did): the caller leaves.
+    __device__ __forceinline__ bool grid_sync()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        target += (unsigned long long)G;
+        if (tid == 0) {
+            __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long n = 0;
+            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++n > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            red[4 * W + 7] = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        return red[4 * W + 7] == 0.0;
+    }
+
+    __device__ __forceinline__ double* rec(int c) const { return xg + (size_t)c * XREC; }
+
+    // Own points and the parity ghosts at x = 0 / pi/2 into LDS; the chunk's
+    // edge points into its exchange record.
+    __device__ __forceinline__ void publish(const double* v0, const double* v1)
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            if (own(k)) U[k * RS + col] = make_double2(v0[k], v1[k]);
+        if (tid == 0) {
+            if (first) {
+                U[(P - 1) * RS] = make_double2(-v0[1], v1[1]);
+                U[(P - 2) * RS] = make_double2(-v0[2], v1[2]);
+                U[(P - 3) * RS] = make_double2(-v0[3], v1[3]);
+            } else {
+                double* r = rec(g) + XU_L;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    r[2 * k] = v0[k];
+                    r[2 * k + 1] = v1[k];
+                }
+            }
+        }
+        if (!last && tid == NL - 1) {
+            double* r = rec(g) + XU_R;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                r[2 * k] = v0[P - 1 - k];
+                r[2 * k + 1] = v1[P - 1 - k];
+            }
+        }
+        if (last && near_end) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int j = i0 + k;
+                if (j >= N - 4 && j <= N - 2) U[slot(2 * (N - 1) - j)] = make_double2(v0[k], -v1[k]);
+            }
+            if (has_nm2) U[slot(N - 1)] = make_double2(0.0, 0.0);
+        }
+    }
+
+    // Sync A and the neighbours' edge points into the ghost columns.
+    __device__ __forceinline__ bool exchange_u()
+    {
+        if (!grid_sync()) return false;
+        if (tid == 0 && !first) {
+            const double* r = rec(g - 1) + XU_R;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) U[(P - 1 - k) * RS] = make_double2(r[2 * k], r[2 * k + 1]);
+        }
+        if (tid == NL - 1 && !last) {
+            const double* r = rec(g + 1) + XU_L;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) U[k * RS + NL + 1] = make_double2(r[2 * k], r[2 * k + 1]);
+        }
+        return true;
+    }
+
+    // Right-hand sides at the published stage input (after exchange_u).  With
+    // `check`, the collapse / non-finite bits of the whole instance are
+    // returned (nothing else is computed when any is set).  Returns -1 when a
+    // grid synchronisation failed.
+    __device__ __forceinline__ int rhs(bool check, double* r0, double* r1)
+    {
+        __syncthreads();  // B0
+        const auto tb = tables();
+        double ko0[P], ko1[P], q[P];
+        {
+            double2 w[P + 6];
+#pragma unroll
+            for (int t = 0; t < P + 6; ++t) {
+                const int tt = t - 3;
+                if (tt < 0) w[t] = U[(P + tt) * RS + col - 1];
+                else if (tt < P) w[t] = U[tt * RS + col];
+                else w[t] = U[(tt - P) * RS + col + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                ko0[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
+                                + 15.0 * w[k + 4].x - 6.0 * w[k + 5].x + w[k + 6].x);
+                ko1[k] = kof * (w[k].y - 6.0 * w[k + 1].y + 15.0 * w[k + 2].y - 20.0 * w[k + 3].y
+                                + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
+                q[k] = own(k) ? w[k + 3].x * w[k + 3].x + w[k + 3].y * w[k + 3].y : 0.0;
+            }
+        }
+        // local prefix sums of p and sigma'
+        double p[P];
+        double ptot = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            p[k] = tab(tb, 0, k) * q[k];
+            ptot += p[k];
+        }
+        const double incl = wave_incl_scan(ptot);
+        if (lane == 63) red[wv] = incl;
+        PE[tid] = p[0];
+        PE[NL + tid] = p[P - 1];
+        if (first && tid == 0) red[4 * W] = p[1];
+        if (has_nm2) {
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                if (i0 + k == N - 2) red[4 * W + 1] = p[k];
+        }
+        __syncthreads();  // B1
+        double carry = incl - ptot, tot = 0.0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            const double t = red[v];
+            if (v < wv) carry += t;
+            tot += t;
+        }
+        double pl, pr;
+        if (tid > 0) {
+            pl = PE[NL + tid - 1];
+        } else if (first) {
+            pl = -red[4 * W];
+        } else {
+            const double2 u = U[(P - 1) * RS];  // point a - 1
+            pl = tab_at(0, a - 1) * (u.x * u.x + u.y * u.y);
+        }
+        if (tid < NL - 1) {
+            pr = PE[tid + 1];
+        } else if (last) {
+            pr = 0.0;
+        } else {
+            const double2 u = U[NL + 1];  // point a + C
+            pr = tab_at(0, a + C) * (u.x * u.x + u.y * u.y);
+        }
+        double sg[P], dp[P], E[P];
+        double R = carry, stot = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            R += p[k];
+            const double pm = (k == 0) ? pl : p[k - 1];
+            const double pp = (k == P - 1) ? pr : p[k + 1];
+            dp[k] = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp);
+            E[k] = exp(-dp[k]);
+            sg[k] = tab(tb, 1, k) * q[k] * E[k];
+            stot += sg[k];
+        }
+        const double incl2 = wave_incl_scan(stot);
+        if (lane == 63) red[W + wv] = incl2;
+        SE[tid] = sg[0];
+        SE[NL + tid] = sg[P - 1];
+        __syncthreads();  // B2
+        double carry2 = incl2 - stot, tot2 = 0.0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            const double t = red[W + v];
+            if (v < wv) carry2 += t;
+            tot2 += t;
+        }
+        // sync B: chunk totals and edge values
+        if (tid == 0) {
+            double* r = rec(g);
+            r[XS_P] = tot;
+            r[XS_S] = tot2;
+            r[XS_SF] = sg[0];
+            if (first) r[XS_P1] = red[4 * W];
+            if (last) r[XS_PN] = red[4 * W + 1];
+        }
+        if (tid == NL - 1 && !last) rec(g)[XS_SL] = sg[P - 1];
+        if (!grid_sync()) return -1;
+        // per-chunk factors F_h and the sigma carry D_g
+        double* fac = red + 4 * W + 8;  // [0,G) F_h, [G,2G) F_h * (sigma' total of h)
+        {
+            const double p1 = rec(0)[XS_P1];
+            double tp = 0.0;
+            for (int c = 0; c < G; ++c) tp += rec(c)[XS_P];
+            const double pN2 = rec(G - 1)[XS_PN];
+            const double dN = -h24 * (24.0 * tp + 2.0 * pN2 + 2.0 * p1);
+            const double shift = bgauge ? dN : 0.0;
+            if (tid < G) {
+                double Cg = 0.0;
+                for (int c = 0; c < tid; ++c) Cg += rec(c)[XS_P];
+                const double Fh = exp(24.0 * h24 * Cg + 2.0 * h24 * p1 + shift);
+                fac[tid] = Fh;
+                fac[G + tid] = Fh * rec(tid)[XS_S];
+            }
+            if (tid == 0) red[4 * W + 2] = dN;
+        }
+        __syncthreads();
+        const double Fg = fac[g];
+        double Dg = 0.0;
+        for (int c = 0; c < g; ++c) Dg += fac[G + c];
+        const double sl = (tid > 0) ? SE[NL + tid - 1]
+                                    : (first ? sg[1] : rec(g - 1)[XS_SL] * fac[g - 1] / Fg);
+        const double sr = (tid < NL - 1) ? SE[tid + 1] : (last ? 0.0 : rec(g + 1)[XS_SF] * fac[g + 1] / Fg);
+        double S[P];
+        {
+            double R2 = carry2;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                R2 += sg[k];
+                const double sm = (k == 0) ? sl : sg[k - 1];
+                const double sp = (k == P - 1) ? sr : sg[k + 1];
+                S[k] = h24 * (24.0 * (Dg + Fg * R2) + Fg * (-12.0 * sg[k] + sm - sp));
+                E[k] *= Fg;
+            }
+        }
+        const double dN = red[4 * W + 2];
+
+        // fluxes
+        double f2_1 = 0.0, f2_2 = 0.0, chk = 0.0;
+        double f1a[3] = {0.0, 0.0, 0.0}, ga[3] = {0.0, 0.0, 0.0};
+        double fb[2][2] = {{0.0, 0.0}, {0.0, 0.0}};  // (f1, g) of the chunk's last two points
+        int cl = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int j = i0 + k;
+            if (own(k)) {
+                const double2 v = U[k * RS + col];
+                const double c3s = tab(tb, 2, k) * tab(tb, 0, k);
+                const double wk = E[k] - c3s * S[k];
+                const double f1 = wk * v.y;
+                const double f2 = wk * v.x;
+                const double gk = tab(tb, 1, k) * f2;
+                if (k == 0) { f1a[0] = f1; ga[0] = gk; }
+                if (k == 1) { f2_1 = f2; f1a[1] = f1; ga[1] = gk; }
+                if (k == 2) { f2_2 = f2; f1a[2] = f1; ga[2] = gk; }
+                if (k == P - 1) { fb[0][0] = f1; fb[0][1] = gk; }
+                if (k == P - 2) { fb[1][0] = f1; fb[1][1] = gk; }
+                if (check) {
+                    if (wk < thr * E[k]) cl = 1;
+                    chk = fma(q[k], 0.0, chk);
+                    chk = fma(wk, 0.0, chk);
+                    chk = fma(E[k], 0.0, chk);
+                }
+                F[k * RS + col] = make_double2(f1, gk);
+                if (last && j >= N - 3 && j <= N - 2) F[slot(2 * (N - 1) - j)] = make_double2(-f1, gk);
+            }
+        }
+        if (tid == 0) {
+            if (first) {
+                F[(P - 1) * RS] = make_double2(f1a[1], -ga[1]);
+                F[(P - 2) * RS] = make_double2(f1a[2], -ga[2]);
+            } else {
+                double* r = rec(g) + XF_L;
+                r[0] = f1a[0];
+                r[1] = ga[0];
+                r[2] = f1a[1];
+                r[3] = ga[1];
+            }
+        }
+        if (tid == NL - 1 && !last) {
+            double* r = rec(g) + XF_R;
+            r[0] = fb[0][0];
+            r[1] = fb[0][1];
+            r[2] = fb[1][0];
+            r[3] = fb[1][1];
+        }
+        if (has_nm2) F[slot(N - 1)] = make_double2(0.0, 0.0);
+        if (check) {
+            if (1.0 < thr) cl = 1;
+            if (!isfinite(dN) || !isfinite(chk)) cl |= 2;
+            const int wcol = __any(cl & 1) ? 1 : 0;
+            const int wnf = __any(cl & 2) ? 2 : 0;
+            if (lane == 0) red[2 * W + wv] = (double)(wcol | wnf);
+        }
+        __syncthreads();  // B3
+        if (check && tid == 0) {
+            int b = 0;
+            for (int v = 0; v < W; ++v) b |= (int)red[2 * W + v];
+            rec(g)[XF_B] = (double)b;
+        }
+        if (!grid_sync()) return -1;  // sync C
+        if (check) {
+            int b = 0;
+            for (int c = 0; c < G; ++c) b |= (int)rec(c)[XF_B];
+            if (b) return b;
+        }
+        if (tid == 0 && !first) {
+            const double* r = rec(g - 1) + XF_R;
+            F[(P - 1) * RS] = make_double2(r[0], r[1]);
+            F[(P - 2) * RS] = make_double2(r[2], r[3]);
+        }
+        if (tid == NL - 1 && !last) {
+            const double* r = rec(g + 1) + XF_L;
+            F[NL + 1] = make_double2(r[0], r[1]);
+            F[RS + NL + 1] = make_double2(r[2], r[3]);
+        }
+        __syncthreads();
+
+        double2 fw[P + 4];
+#pragma unroll
+        for (int t = 0; t < P + 4; ++t) {
+            const int tt = t - 2;
+            if (tt < 0) fw[t] = F[(P + tt) * RS + col - 1];
+            else if (tt < P) fw[t] = F[tt * RS + col];
+            else fw[t] = F[(tt - P) * RS + col + 1];
+        }
+        if (last && near_end) {
+            const int tN = (N - 1) - (i0 - 2);
+            if (tN >= 0 && tN < P + 4) {
+                const double gext = (15.0 * F[slot(N - 2)].y - 6.0 * F[slot(N - 3)].y + F[slot(N - 4)].y) / 10.0;
+#pragma unroll
+                for (int t = 0; t < P + 4; ++t)
+                    if (t == tN) fw[t].y = gext;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double Df1 = (fw[k].x - 8.0 * fw[k + 1].x + 8.0 * fw[k + 3].x - fw[k + 4].x) * i12h;
+            const double Dg = (fw[k].y - 8.0 * fw[k + 1].y + 8.0 * fw[k + 3].y - fw[k + 4].y) * i12h;
+            r0[k] = Df1 + ko0[k];
+            r1[k] = tab(tb, 2, k) * Dg + ko1[k];
+            if (first && k == 0 && tid == 0) {
+                r0[k] = 0.0;
+                r1[k] = 3.0 * ((16.0 * f2_1 - 2.0 * f2_2) * i12h) + ko1[k];
+            }
+            if (!own(k)) {
+                r0[k] = 0.0;
+                r1[k] = 0.0;
+            }
+        }
+        return 0;
+    }
+};
+
+template <int P, int W>
+__global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArgs x)
+{
+    extern __shared__ double lds[];
+    const int b = x.inst;
+    const InstStatus st0 = a.status[b];
+    if (st0.state == ST_COLLAPSED || st0.state == ST_NONFINITE) return;
+    const InstConst ic = a.ic[b];
+    using Ch = Chunk<P, W>;
+    Ch cs;
+    cs.U = reinterpret_cast<double2*>(lds);
+    cs.F = cs.U + Ch::SLOTS;
+    cs.PE = reinterpret_cast<double*>(cs.F);
+    cs.SE = reinterpret_cast<double*>(cs.F + Ch::SLOTS);
+    cs.red = cs.SE + 2 * Ch::NL;
+    cs.tid = threadIdx.x;
+    cs.lane = cs.tid & 63;
+    cs.wv = cs.tid >> 6;
+    cs.g = blockIdx.x;
+    cs.G = x.chunks;
+    cs.a = cs.g * Ch::C;
+    cs.i0 = cs.a + cs.tid * P;
+    cs.col = cs.tid + 1;
+    cs.N = ic.N;
+    cs.first = cs.g == 0;
+    cs.last = cs.g == cs.G - 1;
+    const int N = ic.N;
+    cs.has_nm2 = cs.last && (cs.i0 <= N - 2) && (N - 2 < cs.i0 + P);
+    cs.near_end = cs.last && (cs.i0 + P + 2 >= N - 4) && (cs.i0 <= N - 2);
+    cs.bgauge = a.gauge == 0;
+    cs.h24 = ic.h24;
+    cs.i12h = ic.i12h;
+    cs.kof = ic.kof;
+    cs.thr = a.a_collapse;
+    cs.tabI = gmem(a.tab[b]);
+    cs.tab0 = cs.tabI + (size_t)cs.g * 3 * Ch::C;
+    cs.xg = x.xch;
+    cs.ctr = x.ctr;
+    cs.err = x.err;
+    cs.target = 0;
+    const double dt = ic.dt;
+    const int i0 = cs.i0;
+
+    double un0[P], un1[P], acc0[P], acc1[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const bool o = cs.own(k);
+        un0[k] = o ? a.Phi[ic.off + i0 + k] : 0.0;
+        un1[k] = o ? a.Pi[ic.off + i0 + k] : 0.0;
+        acc0[k] = 0.0;
+        acc1[k] = 0.0;
+    }
+    int stop_bits = 0;
+    bool failed = false;
+    int64_t n = st0.steps;
+    int64_t seg_end = st0.target;
+    if (a.snap_every > 0) {
+        const int64_t nb = (n / a.snap_every + 1) * a.snap_every;
+        if (nb < seg_end) seg_end = nb;
+    }
+    cs.publish(un0, un1);
+    while (n < seg_end && !failed) {
+        for (int s = 0; s < 4; ++s) {
+            if (!cs.exchange_u()) {
+                failed = true;
+                break;
+            }
+            double r0[P], r1[P];
+            const int bits = cs.rhs(s == 0, r0, r1);
+            if (bits < 0) {
+                failed = true;
+                break;
+            }
+            if (bits) {
+                stop_bits = bits;
+                break;
+            }
+            const double c_next = (s == 2) ? dt : 0.5 * dt;
+            const double wacc = (s == 0 || s == 3) ? 1.0 : 2.0;
+            double us0[P], us1[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (s == 0) {
+                    acc0[k] = r0[k];
+                    acc1[k] = r1[k];
+                } else {
+                    acc0[k] = acc0[k] + wacc * r0[k];
+                    acc1[k] = acc1[k] + wacc * r1[k];
+                }
+                if (s < 3) {
+                    us0[k] = un0[k] + c_next * r0[k];
+                    us1[k] = un1[k] + c_next * r1[k];
+                } else {
+                    un0[k] = un0[k] + (dt / 6.0) * acc0[k];
+                    un1[k] = un1[k] + (dt / 6.0) * acc1[k];
+                    us0[k] = un0[k];
+                    us1[k] = un1[k];
+                }
+            }
+            cs.publish(us0, us1);
+        }
+        if (stop_bits || failed) break;
+        ++n;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        if (cs.own(k)) {
+            a.Phi[ic.off + i0 + k] = un0[k];
+            a.Pi[ic.off + i0 + k] = un1[k];
+        }
+    }
+    if (cs.g == 0 && cs.tid == 0) {
+        InstStatus o = st0;
+        o.steps = n;
+        if (failed) {
+            o.state = ST_NONFINITE;
+            o.t_c = -2.0;
+        } else if (stop_bits) {
+            o.state = (stop_bits & 2) ? ST_NONFINITE : ST_COLLAPSED;
+            o.t_c = (double)n * dt;
+        }
+        a.status[b] = o;
+    }
+}
+
+__global__ void big_reset_kernel(unsigned long long* ctr, int* err)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *ctr = 0ull;
+        *err = 0;
+    }
+}
+
+template <int P, int W>
+hipError_t launch_big_t(int chunks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
+{
+    big_reset_kernel<<<dim3(1), dim3(64), 0, s>>>(x.ctr, x.err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = StageLayout<P, W>::lds_doubles * sizeof(double) + (size_t)(3 * 64) * sizeof(double);
+    EvolveArgs ea = a;
+    BigArgs xa = x;
+    void* args[] = {(void*)&ea, (void*)&xa};
+    return hipLaunchCooperativeKernel((const void*)evolve_big_kernel<P, W>, dim3(chunks), dim3(64 * W), args, lds, s);
+}
+
+template <int P, int W>
+hipError_t prepare_big_t(size_t max_lds)
+{
+    const size_t need = StageLayout<P, W>::lds_doubles * sizeof(double) + (size_t)(3 * 64) * sizeof(double);
+    if (need > max_lds) return hipErrorInvalidValue;
+    return hipFuncSetAttribute((const void*)evolve_big_kernel<P, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)need);
+}
+
+}  // namespace
+
+#define ADSCL_BIG_CLASSES(X) \
+    X(4, 4)                  \
+    X(4, 8)
+
+bool big_class_supported(ClassCfg c)
+{
+#define X(p, w) \
+    if (c.P == p && c.W == w) return true;
+    ADSCL_BIG_CLASSES(X)
+#undef X
+    return false;
+}
+
+size_t big_lds_bytes(ClassCfg c)
+{
+    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * 64) * sizeof(double);
+}
+
+hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds)
+{
+#define X(p, w) \
+    if (c.P == p && c.W == w) return prepare_big_t<p, w>(max_lds);
+    ADSCL_BIG_CLASSES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_evolve_big(ClassCfg c, int chunks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
+{
+#define X(p, w) \
+    if (c.P == p && c.W == w) return launch_big_t<p, w>(chunks, a, x, s);
+    ADSCL_BIG_CLASSES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace adscl

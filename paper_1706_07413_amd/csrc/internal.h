@@ -78,6 +78,22 @@ hipError_t prepare_evolve(ClassCfg c, size_t max_lds);
 // full: every instance of the launch has N - 1 == 64 W P.
 hipError_t launch_evolve(ClassCfg c, bool full, int n_blocks, const EvolveArgs& a, hipStream_t s);
 
+// One large instance over `chunks` workgroups of a (P, W) chunk class
+// (cooperative launch): its index, the exchange records [chunks][32], and an
+// arrival counter and error flag of its own.
+struct BigArgs {
+    int32_t inst;
+    int32_t chunks;
+    double* xch;
+    unsigned long long* ctr;
+    int* err;
+};
+bool big_class_supported(ClassCfg c);
+size_t big_lds_bytes(ClassCfg c);
+hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds);
+hipError_t launch_evolve_big(ClassCfg c, int chunks, const EvolveArgs& a, const BigArgs& x, hipStream_t s);
+constexpr int kBigMaxChunks = 96;
+
 // Initial data: Pi = (2 eps/pi) exp(-4 tan^2 x/(pi^2 sigma^2)), Phi = 0 (pins applied).
 hipError_t launch_init_gaussian(int n_inst, const InstConst* ic, const double* eps, const double* sigma,
                                 double* Phi, double* Pi, int64_t max_N, hipStream_t s);
@@ -102,11 +118,19 @@ hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, doub
 hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi, const double* Pi,
                               const double* A, const double* delta, const double* m, double* out,
                               hipStream_t s);
-// Spectrum: per instance projection of sqrt(A) Pi, sqrt(A) Phi on weight tables
-// wPi[b] = h t2 e_j, wPhi[b] = h t2 e_j'/omega_j, each [Jtab][N].
-hipError_t launch_spectrum(int n_inst, const InstConst* ic, const double* Phi, const double* Pi,
-                           const double* A, const double* const* wPi, const double* const* wPhi, int J,
-                           double* E, double* Pihat, double* Phihat, hipStream_t s);
+// Spectrum rows: one state of one instance, as element offsets of its Phi, Pi
+// and A rows from a common base, and its output row.
+struct SpecRow {
+    int64_t phi;
+    int64_t pi;
+    int64_t a;
+    int64_t out;
+};
+// Projection of sqrt(A) Pi, sqrt(A) Phi of `n_rows` rows of grid size N on the
+// weight tables wPi = h t2 e_j, wPhi = h t2 e_j'/omega_j ([Jtab][N]); outputs
+// [out][J] (any may be NULL).  FP64 MFMA.
+hipError_t launch_spectrum_rows(const double* base, const SpecRow* rows, int n_rows, int N, const double* wPi,
+                                const double* wPhi, int J, double* E, double* Pihat, double* Phihat, hipStream_t s);
 
 // ---- discrete adjoint -------------------------------------------------------
 
@@ -170,5 +194,24 @@ hipError_t launch_adj_finish(int n_inst, const InstConst* ic, const InstStatus* 
                              int64_t total, const double* const* emode, const double* eps, int Jc,
                              const double* E0, const double* ET, int J, double* L, double* dLdc,
                              int32_t* valid, hipStream_t s);
+
+// Fill n doubles with v (a kernel, so that it can sit in a captured graph).
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// Mark instances with active[b] == 0 as COLLAPSED (the kernels skip them).
+hipError_t launch_mask(int n_inst, InstStatus* st, const int32_t* active, hipStream_t s);
+
+// State of the batched gradient descent, on the device.
+struct GdState {
+    double* s;        // [n_inst] step fraction
+    double* Lprev;    // [n_inst] objective of the previous iteration
+    int32_t* active;  // [n_inst] 0 once the instance collapsed
+    int32_t* iter;    // [1] iteration counter
+};
+hipError_t launch_gd_init(int n_inst, double step0, const GdState& g, hipStream_t s);
+// Iteration iter: L_hist[iter][b] = L_b (NaN for masked instances); an invalid
+// instance is masked; s_b halves when L_b grew; c_b -= s_b |c_b| / |g_b| g_b;
+// then iter += 1.
+hipError_t launch_gd_update(int n_inst, int Jc, double* c, const double* grad, const double* L, const int32_t* valid,
+                            const GdState& g, double* L_hist, hipStream_t s);
 
 }  // namespace adscl

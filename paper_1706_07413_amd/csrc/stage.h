@@ -63,13 +63,40 @@ __device__ __forceinline__ double wave_incl_scan(double v)
     return v;
 }
 
+// A lane-interleaved global array of doubles, [field][P][64 W]: entry (f, k) of
+// lane l at ((f P + k) 64 W + l).  Held as a uniform base and the lane's byte
+// offset, the latter opaque to the compiler, so that each access is a scalar
+// base plus a 32-bit vector offset formed where it is used (rather than a
+// 64-bit address per entry computed once and kept, or spilled, for the whole
+// kernel).  Make a fresh view per phase with lane_arr().
+template <int P, int NL>
+struct LaneArr {
+    ADSCL_GLOBAL char* base;
+    unsigned o;
+    __device__ __forceinline__ ADSCL_GLOBAL double* at(int f, int k) const
+    {
+        return (ADSCL_GLOBAL double*)(base + (o + (unsigned)((f * P + k) * NL * 8)));
+    }
+    __device__ __forceinline__ double ld(int f, int k) const { return *at(f, k); }
+    __device__ __forceinline__ void st(int f, int k, double v) const { *at(f, k) = v; }
+};
+
+template <int P, int NL>
+__device__ __forceinline__ LaneArr<P, NL> lane_arr(ADSCL_GLOBAL double* base, int lane_id)
+{
+    unsigned o = (unsigned)lane_id * 8u;
+    asm volatile("" : "+v"(o));
+    return LaneArr<P, NL>{(ADSCL_GLOBAL char*)base, o};
+}
+
 template <int P, int W>
 struct StageLayout {
     static constexpr int NL = 64 * W;      // lanes per instance
     static constexpr int RS = NL + 2;      // LDS row: column 0 = lane -1, NL+1 = lane NL
     static constexpr int SLOTS = P * RS;
-    // U and F: 2 x SLOTS pairs; sigma edges: 2 NL; reductions: 4 W + 8
-    static constexpr size_t lds_doubles = (size_t)4 * SLOTS + 2 * NL + 4 * W + 8;
+    // U and F: 2 x SLOTS pairs; sigma edges: 2 NL; reductions: 4 W + 8; with
+    // P >= 8, a separate region for the p edges (2 NL)
+    static constexpr size_t lds_doubles = (size_t)4 * SLOTS + 2 * NL + 4 * W + 8 + (P >= 8 ? 2 * NL : 0);
 };
 
 template <int P, int W, bool FULL>
@@ -79,6 +106,12 @@ struct Stage {
     static constexpr int SLOTS = P * RS;
     static_assert(P >= 4, "lane 0 must own grid points 0..3");
 
+    // Full lanes with P >= 8 exchange only lane edges through LDS: the lane's
+    // own points stay in registers, neighbours read the first and last three
+    // stage-input points (UE, double-buffered by stage) and the first and last
+    // two fluxes (FE).  Every other case keeps whole lane-interleaved rows.
+    static constexpr bool EDGE = FULL && P >= 8;
+
     double2* U;     // (Phi_s, Pi_s) rows
     double2* F;     // (f1, g) rows; p first / last per lane between B0 and B2
     double* PE;
@@ -86,6 +119,7 @@ struct Stage {
     double* red;    // [0,W) delta~ totals, [W,2W) S totals, [2W,3W) flags,
                     // [3W,4W) spare, 4W: p_1, 4W+1: p_{N-2}
     int tid, lane, wv, i0, col, N;
+    int buf;        // UE buffer of the last publish (EDGE)
     bool has_nm2, near_end, bgauge;
     double h, dt, h24, i12h, kof, thr;
     const ADSCL_GLOBAL double* tab0;
@@ -100,6 +134,8 @@ struct Stage {
         PE = reinterpret_cast<double*>(F);
         SE = reinterpret_cast<double*>(F + SLOTS);
         red = SE + 2 * NL;
+        if (EDGE) PE = red + 4 * W + 8;  // no B0 on the edge path: p edges get their own region
+        buf = 0;
         tid = threadIdx.x;
         lane = tid & 63;
         wv = tid >> 6;
@@ -121,6 +157,12 @@ struct Stage {
     }
 
     __device__ __forceinline__ bool own(int k) const { return FULL || (i0 + k <= N - 2); }
+
+    // Edge rows (EDGE): UE buffer b row r (r 0..2: the lane's points 0..2, r 3..5:
+    // points P-1, P-2, P-3) and FE row r (r 0, 1: fluxes of points 0, 1; r 2, 3:
+    // of points P-1, P-2); column l + 1 for lane l, 0 and NL + 1 the ghosts.
+    __device__ __forceinline__ double2* ue(int b, int r) const { return b == 0 ? U + r * RS : F + (2 + r) * RS; }
+    __device__ __forceinline__ double2* fe(int r) const { return r < 2 ? F + r * RS : U + (4 + r) * RS; }
 
     // LDS index of point j, -P <= j < 64 W P + P
     __device__ __forceinline__ int slot(int j) const
@@ -154,6 +196,25 @@ struct Stage {
     // Phi odd / Pi even about x = 0, Phi even / Pi odd about pi/2, Phi = Pi = 0 at pi/2.
     __device__ __forceinline__ void publish(const double* v0, const double* v1)
     {
+        if constexpr (EDGE) {
+            buf ^= 1;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                ue(buf, r)[col] = make_double2(v0[r], v1[r]);
+                ue(buf, 3 + r)[col] = make_double2(v0[P - 1 - r], v1[P - 1 - r]);
+            }
+            if (tid == 0) {
+                ue(buf, 3)[0] = make_double2(-v0[1], v1[1]);
+                ue(buf, 4)[0] = make_double2(-v0[2], v1[2]);
+                ue(buf, 5)[0] = make_double2(-v0[3], v1[3]);
+            }
+            if (tid == NL - 1) {
+                ue(buf, 0)[NL + 1] = make_double2(0.0, 0.0);
+                ue(buf, 1)[NL + 1] = make_double2(v0[P - 1], -v1[P - 1]);
+                ue(buf, 2)[NL + 1] = make_double2(v0[P - 2], -v1[P - 2]);
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k)
             if (own(k)) U[k * RS + col] = make_double2(v0[k], v1[k]);
@@ -266,11 +327,14 @@ struct Stage {
     // run before B3 and the function returns their workgroup-wide bits
     // (1 collapsed, 2 non-finite) without computing r when any is set.
     // r0, r1: Phi_t, Pi_t of the own points (0 at pinned points).  KEEP: also
-    // stores e^-delta and S of the lane's points to ES ([2][P][64 W], lane-interleaved).
+    // stores e^-delta and S of the lane's points to fields fE and fE + 1 of ES.
+    // v0, v1: the published stage input of the own points (read on the edge
+    // path, where it is not in LDS).
     template <bool KEEP = false>
-    __device__ __forceinline__ int rhs(bool check, bool frozen, double* r0, double* r1,
-                                       ADSCL_GLOBAL double* ES = nullptr)
+    __device__ __forceinline__ int rhs(bool check, bool frozen, const double* v0, const double* v1, double* r0,
+                                       double* r1, ADSCL_GLOBAL double* ES = nullptr, int fE = 0)
     {
+        if constexpr (EDGE) return rhs_edge<KEEP>(check, frozen, v0, v1, r0, r1, ES, fE);
         __syncthreads();  // B0
         const auto tb = tables();
         double ko0[P], ko1[P], q[P];
@@ -302,10 +366,11 @@ struct Stage {
             for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
         }
         if constexpr (KEEP) {
+            const auto es = lane_arr<P, NL>(ES, tid);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                ES[k * NL + tid] = E[k];
-                ES[(P + k) * NL + tid] = S[k];
+                es.st(fE, k, E[k]);
+                es.st(fE + 1, k, S[k]);
             }
         }
 
@@ -404,6 +469,120 @@ struct Stage {
                 r0[k] = 0.0;
                 r1[k] = 0.0;
             }
+        }
+        return 0;
+    }
+
+    // rhs on the edge path.  No barrier before the scans: the stage input is in
+    // registers and its edges were published before the first scan barrier;
+    // both edge buffers' last readers are separated from their next writers by
+    // at least one barrier of the next stage.
+    template <bool KEEP>
+    __device__ __forceinline__ int rhs_edge(bool check, bool frozen, const double* v0, const double* v1, double* r0,
+                                            double* r1, ADSCL_GLOBAL double* ES, int fE)
+    {
+        const auto tb = tables();
+        double q[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) q[k] = v0[k] * v0[k] + v1[k] * v1[k];
+        double dl[P], E[P], S[P];
+        double dN = 0.0, tot2 = 0.0;
+        if (!frozen) {
+            constraints(q, dl, E, S, dN, tot2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
+        }
+        if constexpr (KEEP) {
+            const auto es = lane_arr<P, NL>(ES, tid);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                es.st(fE, k, E[k]);
+                es.st(fE + 1, k, S[k]);
+            }
+        }
+        double ff[P], fg[P], chk = 0.0, f2_1 = 0.0, f2_2 = 0.0;
+        int cl = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double c3s = tab(tb, 2, k) * tab(tb, 0, k);
+            const double wk = E[k] - c3s * S[k];
+            const double f2 = wk * v0[k];
+            ff[k] = wk * v1[k];
+            fg[k] = tab(tb, 1, k) * f2;
+            if (k == 1) f2_1 = f2;
+            if (k == 2) f2_2 = f2;
+            if (check) {
+                if (wk < thr * E[k]) cl = 1;
+                chk = fma(q[k], 0.0, chk);
+                chk = fma(wk, 0.0, chk);
+                chk = fma(E[k], 0.0, chk);
+            }
+        }
+        fe(0)[col] = make_double2(ff[0], fg[0]);
+        fe(1)[col] = make_double2(ff[1], fg[1]);
+        fe(2)[col] = make_double2(ff[P - 1], fg[P - 1]);
+        fe(3)[col] = make_double2(ff[P - 2], fg[P - 2]);
+        if (tid == 0) {  // f1 even, g odd about x = 0
+            fe(2)[0] = make_double2(ff[1], -fg[1]);
+            fe(3)[0] = make_double2(ff[2], -fg[2]);
+        }
+        if (tid == NL - 1) {
+            // f1_{N-1} = 0, g_{N-1} the even 6th-order extrapolation; ghost N
+            fe(0)[NL + 1] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
+            fe(1)[NL + 1] = make_double2(-ff[P - 1], fg[P - 1]);
+        }
+        if (check) {
+            if (1.0 < thr) cl = 1;
+            if (!isfinite(dN) || !isfinite(chk)) cl |= 2;
+            const int wcol = __any(cl & 1) ? 1 : 0;
+            const int wnf = __any(cl & 2) ? 2 : 0;
+            if (lane == 0) red[2 * W + wv] = (double)(wcol | wnf);
+        }
+        __syncthreads();  // B3
+        if (check) {
+            int fl_ = 0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) fl_ |= (int)red[2 * W + v];
+            if (fl_) return fl_;
+        }
+        double ko0[P], ko1[P];
+        {
+            double2 w[P + 6];  // points i0-3 .. i0+P+2
+            w[0] = ue(buf, 5)[tid];
+            w[1] = ue(buf, 4)[tid];
+            w[2] = ue(buf, 3)[tid];
+#pragma unroll
+            for (int k = 0; k < P; ++k) w[3 + k] = make_double2(v0[k], v1[k]);
+            w[P + 3] = ue(buf, 0)[tid + 2];
+            w[P + 4] = ue(buf, 1)[tid + 2];
+            w[P + 5] = ue(buf, 2)[tid + 2];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                ko0[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
+                                + 15.0 * w[k + 4].x - 6.0 * w[k + 5].x + w[k + 6].x);
+                ko1[k] = kof * (w[k].y - 6.0 * w[k + 1].y + 15.0 * w[k + 2].y - 20.0 * w[k + 3].y
+                                + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
+            }
+        }
+        double2 fw[P + 4];  // points i0-2 .. i0+P+1
+        fw[0] = fe(3)[tid];
+        fw[1] = fe(2)[tid];
+#pragma unroll
+        for (int k = 0; k < P; ++k) fw[2 + k] = make_double2(ff[k], fg[k]);
+        fw[P + 2] = fe(0)[tid + 2];
+        fw[P + 3] = fe(1)[tid + 2];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double Df1 = (fw[k].x - 8.0 * fw[k + 1].x + 8.0 * fw[k + 3].x - fw[k + 4].x) * i12h;
+            const double Dg = (fw[k].y - 8.0 * fw[k + 1].y + 8.0 * fw[k + 3].y - fw[k + 4].y) * i12h;
+            r0[k] = Df1 + ko0[k];
+            r1[k] = tab(tb, 2, k) * Dg + ko1[k];
+        }
+        if (tid == 0) {
+            // Phi_0 = 0; lim tan^-2 (tan^2 f2)' = 3 f2'(0) with f2 odd about x = 0
+            r0[0] = 0.0;
+            r1[0] = 3.0 * ((16.0 * f2_1 - 2.0 * f2_2) * i12h) + ko1[0];
         }
         return 0;
     }

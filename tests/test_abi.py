@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("n_grid", [[16], [15], [4099], [513, 514], [1]])
+@pytest.mark.parametrize("n_grid", [[16], [15], [65539], [16386], [513, 514], [1]])
 def test_create_rejects_bad_grid_sizes_before_touching_the_gpu(n_grid):
     L = adscl.lib()
     N = np.asarray(n_grid, np.int32)
@@ -60,3 +60,24 @@ def test_null_context_calls_fail_cleanly():
     assert L.adscl_sync(None) == adscl.EINVAL
     assert L.adscl_step(None, 1, 1.0, 0, 0, None, 0) == adscl.EINVAL
     assert L.adscl_status(None, None, None, None, None, None) == adscl.EINVAL
+    assert L.adscl_spectrum(None, 4, None, None, None, 0) == adscl.EINVAL
+    assert L.adscl_spectrum_snaps(None, 4, 1, None, None, None, None, 0) == adscl.EINVAL
+    assert L.adscl_adjoint(None, None, None, 4, 4, 1.0, 8, None, None, None, 0) == adscl.EINVAL
+    assert L.adscl_descend(None, None, None, 4, 4, 1.0, 8, 2, 0.05, 0, None, None, 0) == adscl.EINVAL
+    assert L.adscl_constraints(None, None, 0) == adscl.EINVAL
+    assert L.adscl_get_state(None, None, None, None, None, None, 0) == adscl.EINVAL
+    assert L.adscl_kernel_stats(None, 0, None, None, None, None, None, None) == adscl.EINVAL
+    assert L.adscl_last_error(None) is not None
+
+
+def test_create_accepts_large_grids_before_touching_the_gpu():
+    """N above 4097 (up to 65537) passes validation; with no GPU here the call
+    then fails on the device, not on the arguments."""
+    L = adscl.lib()
+    N = np.asarray([16385, 65537], np.int32)
+    cfg = adscl.Config(len(N), N.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0.25, 0.5, 0.01, 0, 0, 0)
+    h = ctypes.c_void_p()
+    rc = L.adscl_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert rc != adscl.EINVAL, L.adscl_last_error(None)
+    if rc == adscl.OK:
+        L.adscl_destroy(h)

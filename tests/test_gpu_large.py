@@ -1,0 +1,98 @@
+"""Parity of the multi-workgroup path (grids above 4097 points) with the oracle.
+
+A large instance is cut into chunks of 2048 points, one workgroup each, that
+exchange stage-input halos, scan carries and flux halos through global memory
+every stage.  The computation is the same scheme with the prefix sums
+re-associated (a chunk's carry enters as one factor), so the fields must match
+the oracle to the same 1e-11 relative max-norm as the single-workgroup path.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1706_07413_amd import adscl
+from paper_1706_07413_amd import inputs as I
+from test_gpu_parity import FIELDS, assert_close, gpu_state
+
+pytestmark = pytest.mark.gpu
+
+
+def test_two_mode_data_on_16385_points():
+    """The 16385-point two-mode workload 0.05 (e_0 + 0.6 e_1): 8 chunks, 200
+    steps, with snapshots every 50 steps."""
+    import torch
+    c = I.config1()
+    N = int(c["N"][0])
+    print("large N", N, flush=True)
+    b = adscl.Batch(c["N"], gauge=c["gauge"], a_collapse=c["a_collapse"], n_modes=8)
+    b.init_modes(c["eps"], np.ascontiguousarray(c["c"]))
+    snaps = torch.zeros((5, 5, b.total), dtype=torch.float64, device="cuda")
+    b.step(200, 1e9, snap_every=50, snaps=snaps)
+    st = b.status()
+    assert st["steps"][0] == 200 and st["state"][0] == adscl.RUNNING
+    Phi, Pi = O.init_modes(N, float(c["eps"][0]), c["c"][0])
+    ref = O.evolve(Phi, Pi, 200, gauge=c["gauge"], snap_every=50, n_slots=5)
+    g = gpu_state(b)
+    for f in FIELDS:
+        assert_close(g[f], ref[f], "N=%d %s" % (N, f))
+    sn = snaps.cpu().numpy()
+    for s in range(5):
+        for f in range(5):
+            assert_close(sn[s, f], ref["snaps"][s, f], "snapshot %d %s" % (s, FIELDS[f]))
+
+
+@pytest.mark.parametrize("gauge", [O.GAUGE_BOUNDARY, O.GAUGE_ORIGIN])
+def test_ragged_chunks_with_small_instances_in_one_batch(gauge):
+    """N = 10001 (chunks of 2048, 1808 and the end in the last) and N = 6145
+    next to small instances; strong Gaussian data, 300 steps."""
+    Ns = np.array([10001, 129, 6145, 4097], np.int32)
+    eps = np.array([6.0, 3.0, 5.0, 4.0])
+    sig = np.array([0.2, 0.25, 0.15, 0.2])
+    print("large ragged gauge", gauge, flush=True)
+    b = adscl.Batch(Ns, gauge=gauge, a_collapse=0.0)
+    b.init_gaussian(eps, sig)
+    b.step(300, 1e9)
+    st = b.status()
+    g = gpu_state(b)
+    for i, N in enumerate(Ns):
+        Phi, Pi = O.init_gaussian(int(N), float(eps[i]), float(sig[i]))
+        ref = O.evolve(Phi, Pi, 300, gauge=gauge)
+        assert st["steps"][i] == ref["steps"]
+        for f in FIELDS:
+            assert_close(b.split(g[f])[i], ref[f], "N=%d %s" % (N, f))
+
+
+def test_collapse_of_a_large_instance_at_the_oracle_step():
+    """A pulse whose min A falls through 0.2 after about 1500 steps on 4609
+    points (chunks of 2048, 2048, 512): every chunk stops at the same step, the
+    oracle's."""
+    N, eps, sig, thr = 4609, 60.0, 0.08, 0.2
+    print("large collapse", flush=True)
+    b = adscl.Batch([N], a_collapse=thr)
+    b.init_gaussian(np.array([eps]), np.array([sig]))
+    b.step(2000, 1e9)
+    st = b.status()
+    Phi, Pi = O.init_gaussian(N, eps, sig)
+    ref = O.evolve(Phi, Pi, 2000, a_collapse=thr)
+    assert ref["state"] == O.COLLAPSED, ref["state"]
+    assert st["state"][0] == adscl.COLLAPSED and st["steps"][0] == ref["steps"]
+    g = gpu_state(b)
+    for f in FIELDS:
+        assert_close(g[f], ref[f], "collapsed N=%d %s" % (N, f))
+
+
+def test_large_instance_equals_itself_alone_and_chunked_calls():
+    """Bitwise: a large instance in a batch equals it alone, and 3 calls of 40
+    steps equal one call of 120."""
+    Ns = np.array([8193, 257], np.int32)
+    b = adscl.Batch(Ns)
+    b.init_gaussian(np.array([5.0, 2.0]), np.array([0.2, 0.2]))
+    b.step(120, 1e9)
+    g = gpu_state(b)
+    b1 = adscl.Batch(Ns[:1])
+    b1.init_gaussian(np.array([5.0]), np.array([0.2]))
+    for _ in range(3):
+        b1.step(40, 1e9)
+    g1 = gpu_state(b1)
+    for f in FIELDS:
+        assert np.array_equal(b.split(g[f])[0], g1[f]), f

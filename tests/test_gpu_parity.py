@@ -252,3 +252,34 @@ def test_full_size_workload_launch_sampled():
     for i in picks:
         ref = oracle_gauss(int(c["N"][i]), c["eps"][i], c["sigma"][i], 32, a_collapse=c["a_collapse"])
         compare_instance(b, st, i, ref, "inst %d" % i)
+
+
+def test_spectrum_of_snapshot_batches():
+    """Mode energies of stored snapshots (two-mode data 0.05 (e_0 + 0.6 e_1) and
+    a 3-mode variant), 9 snapshots every 64 steps of three instances of two grid
+    sizes: 18 + 9 states in two matrix products with ragged row tiles, 40 modes
+    (a ragged mode tile)."""
+    import torch
+    Ns = np.array([1025, 4097, 1025], np.int32)
+    coef = np.array([[1.0, 0.6, 0.0], [1.0, 0.6, 0.0], [0.5, -0.4, 0.3]])
+    eps = np.array([0.05, 0.05, 0.2])
+    J, every, slots = 40, 64, 9
+    b = adscl.Batch(Ns, n_modes=64)
+    b.init_modes(eps, coef)
+    snaps = torch.zeros((slots, 5, b.total), dtype=torch.float64, device="cuda")
+    b.step(every * (slots - 1), 1e9, snap_every=every, snaps=snaps)
+    E, P, F = b.spectrum_snaps(J, snaps)
+    E, P, F = E.cpu().numpy(), P.cpu().numpy(), F.cpu().numpy()
+    for i, N in enumerate(Ns):
+        Phi, Pi = O.init_modes(int(N), float(eps[i]), coef[i])
+        ref = O.evolve(Phi, Pi, every * (slots - 1), snap_every=every, n_slots=slots)
+        for sl in range(slots):
+            S = ref["snaps"][sl]
+            Eo, Po, Fo = O.spectrum(S[0], S[1], S[2], J)
+            assert_close(E[sl, i], Eo, "E slot %d inst %d" % (sl, i))
+            assert_close(P[sl, i], Po, "Pihat slot %d inst %d" % (sl, i))
+            if sl:
+                assert_close(F[sl, i], Fo, "Phihat slot %d inst %d" % (sl, i))
+    # the current-state call agrees with the last snapshot
+    E1, P1, F1 = b.spectrum(J)
+    assert np.array_equal(E1, E[-1]) and np.array_equal(P1, P[-1])

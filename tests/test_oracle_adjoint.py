@@ -157,3 +157,31 @@ def test_linear_limit_objective_vanishes():
     # L scales as eps^8 (the drift of E_j ~ eps^4 itself scales as eps^4)
     assert 200 < r2["L"] / r1["L"] < 320
     assert np.max(np.abs(r1["grad"])) < 1e-3 * np.max(np.abs(r1["E0"]))
+
+
+def test_descend_decreases_the_objective_with_steps_of_the_stated_length():
+    """With a small step the gradient is a descent direction: every iteration
+    lowers L (first-order decrease s |c| |g| > second-order terms), and each
+    update moves c by exactly s |c| in Euclidean norm."""
+    Ns = [33, 65]
+    eps = [0.5, 0.4]
+    r = np.random.default_rng(21)
+    c0 = r.standard_normal((2, 6)) * np.exp(-np.arange(6) / 4)
+    iters, step0 = 4, 0.01
+    c, hist, active = O.descend(Ns, eps, c0, J=3, T=0.1, K=8, iters=iters, step0=step0)
+    assert list(active) == [1, 1]
+    assert np.all(np.diff(hist, axis=0) < 0), hist
+    c1, _, _ = O.descend(Ns, eps, c0, J=3, T=0.1, K=8, iters=1, step0=step0)
+    for b in range(2):
+        step = np.linalg.norm(c1[b] - c0[b])
+        assert abs(step - step0 * np.linalg.norm(c0[b])) <= 1e-13 * np.linalg.norm(c0[b])
+
+
+def test_descend_masks_a_collapsing_instance():
+    c0 = np.array([[1.0, 0.8, 0.6, 0.4, 0.2, 0.1], [0.3, -0.2, 0.1, 0.0, 0.05, 0.02]])
+    c, hist, active = O.descend([129, 65], [0.8, 0.2], c0, J=3, T=1.0, K=64, iters=2, step0=0.01,
+                                a_collapse=0.15)
+    assert list(active) == [0, 1]
+    assert np.array_equal(c[0], c0[0])
+    assert np.isfinite(hist[0, 0]) and np.isnan(hist[1, 0])
+    assert np.all(np.isfinite(hist[:, 1]))
