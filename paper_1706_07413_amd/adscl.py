@@ -53,6 +53,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libadscl.so is not built (%s); run python -m paper_1706_07413_amd.build" % LIB_PATH)
+    # torch ships a HIP runtime under the same soname as the system one the
+    # library links; loading torch first makes the library bind to that one
+    # instance, the only process layout in which device pointers and streams
+    # are shared with torch.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "adscl_create": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.POINTER(_vp)]),
