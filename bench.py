@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient-rate leg")
     ap.add_argument("--adjoint-t", type=float, default=1.0, help="time window of the adjoint leg")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg and print its result (for profiling it)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the workload, run a plain device copy of this many bytes "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -169,6 +171,9 @@ def main():
     from paper_1706_07413_amd import inputs as I
 
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_rate(adscl, args.adjoint_t)}))
+        return
     cfg = I.config2()
     T = args.t_end
     eps = torch.tensor(cfg["eps"], dtype=torch.float64, device="cuda")
@@ -193,11 +198,12 @@ def main():
     elapsed = time.perf_counter() - t0
     value = work / elapsed
 
-    # roofline of the dominant launch (longest class launch of the last pass)
+    # roofline of the dominant launch (the class launch of the last pass that
+    # did the most grid-point updates)
     classes, cls = batch.kernel_stats()
-    k = int(np.argmax([c["last_ms"] for c in classes]))
-    mem = cls == k
-    unit_steps = pt_steps(np.asarray(cfg["N"])[mem], st["steps"][mem])
+    work_k = [pt_steps(np.asarray(cfg["N"])[cls == j], st["steps"][cls == j]) for j in range(len(classes))]
+    k = int(np.argmax(work_k))
+    unit_steps = work_k[k]
     ms = classes[k]["last_ms"]
     achieved = unit_steps * 4 * FLOP_PER_PT_STAGE / (ms * 1e-3) / 1e12
     states = np.bincount(st["state"], minlength=4)

@@ -33,9 +33,9 @@ def common_flags():
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()]
+    cmd = [hipcc(), "--offload-arch=" + ARCH]
     if src.endswith(".hip"):
-        cmd += ["--offload-arch=" + ARCH, "-x", "hip"]
+        cmd += ["-x", "hip"]
     cmd += common_flags() + ["-I", os.path.join(HERE, "..", "include"), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

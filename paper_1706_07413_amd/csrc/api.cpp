@@ -109,7 +109,9 @@ int fail(adscl_ctx* c, int code, const std::string& msg)
     } while (0)
 
 // Kernel configuration for grid size N: the smallest lane capacity 64 W P that
-// holds the N-1 evolved points.  ADSCL_TUNE="N:PxW,..." overrides per N.
+// holds the N-1 evolved points, taking P = 8 over W = 8 at 2048 points (four
+// wavefronts, one per SIMD, so that two instances can share a compute unit).
+// ADSCL_TUNE="N:PxW,..." overrides per N.
 ClassCfg choose_class(int N)
 {
     if (const char* t = std::getenv("ADSCL_TUNE")) {
@@ -126,7 +128,7 @@ ClassCfg choose_class(int N)
             pos = end + 1;
         }
     }
-    static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 8}};
+    static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {8, 8}};
     for (const ClassCfg& c : pref)
         if (64 * c.W * c.P >= N - 1) return c;
     return ClassCfg{0, 0};
