@@ -17,6 +17,8 @@
 // it wrote), then runs the four stage adjoints in reverse.
 #include <math.h>
 
+#include <algorithm>
+
 #include "stage.h"
 
 namespace adscl {
@@ -605,7 +607,7 @@ __global__ void gd_tick_kernel(GdState g)
 template <int P, int W>
 constexpr size_t lds_bytes_for()
 {
-    return StageLayout<P, W>::lds_doubles * sizeof(double);
+    return std::max(Stage<P, W, true>::lds_doubles, Stage<P, W, false>::lds_doubles) * sizeof(double);
 }
 
 template <int P, int W>

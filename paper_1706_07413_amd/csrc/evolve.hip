@@ -25,6 +25,8 @@
 //
 // The stage machinery (LDS layout, parity ghosts, the two scans, fluxes)
 // lives in stage.h, shared with the adjoint kernel's forward recomputation.
+#include <algorithm>
+
 #include "stage.h"
 
 namespace adscl {
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     const InstConst ic = a.ic[b];
     const int64_t off = ic.off;
     const bool frozen = a.frozen != 0;
-    Stage<P, W, FULL> sg;
+    Stage<P, W, FULL, true> sg;
     sg.setup(lds, ic, a.tab[b], a.gauge, a.a_collapse);
     const int N = sg.N, i0 = sg.i0;
     const double dt = sg.dt;
@@ -155,33 +157,32 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     }
 }
 
-template <int P, int W>
+template <int P, int W, bool FULL>
 constexpr size_t lds_bytes_for()
 {
-    return StageLayout<P, W>::lds_doubles * sizeof(double);
+    return Stage<P, W, FULL, true>::lds_doubles * sizeof(double);
 }
 
 template <int P, int W>
 hipError_t launch_t(bool full, int n_blocks, const EvolveArgs& a, hipStream_t s)
 {
-    const size_t lds = lds_bytes_for<P, W>();
     if (full)
-        evolve_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), lds, s>>>(a);
+        evolve_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), lds_bytes_for<P, W, true>(), s>>>(a);
     else
-        evolve_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), lds, s>>>(a);
+        evolve_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), lds_bytes_for<P, W, false>(), s>>>(a);
     return hipGetLastError();
 }
 
 template <int P, int W>
 hipError_t prepare_t(size_t max_lds)
 {
-    const size_t need = lds_bytes_for<P, W>();
-    if (need > max_lds) return hipErrorInvalidValue;
+    const size_t nf = lds_bytes_for<P, W, true>(), np = lds_bytes_for<P, W, false>();
+    if (nf > max_lds || np > max_lds) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void*)evolve_kernel<P, W, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)nf);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)evolve_kernel<P, W, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)np);
 }
 
 }  // namespace
@@ -213,8 +214,11 @@ bool class_supported(ClassCfg c)
 
 size_t evolve_lds_bytes(ClassCfg c)
 {
-    return (size_t)(4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + (c.P >= 8 ? 2 * 64 * c.W : 0)) *
-           sizeof(double);
+#define X(p, w) \
+    if (c.P == p && c.W == w) return std::max(lds_bytes_for<p, w, true>(), lds_bytes_for<p, w, false>());
+    ADSCL_CLASSES(X)
+#undef X
+    return 0;
 }
 
 hipError_t prepare_evolve(ClassCfg c, size_t max_lds)

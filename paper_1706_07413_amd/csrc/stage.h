@@ -99,27 +99,40 @@ struct StageLayout {
     static constexpr size_t lds_doubles = (size_t)4 * SLOTS + 2 * NL + 4 * W + 8 + (P >= 8 ? 2 * NL : 0);
 };
 
-template <int P, int W, bool FULL>
+template <int P, int W, bool FULL, bool FWD = false>
 struct Stage {
     static constexpr int NL = 64 * W;
     static constexpr int RS = NL + 2;
     static constexpr int SLOTS = P * RS;
     static_assert(P >= 4, "lane 0 must own grid points 0..3");
 
-    // Full lanes with P >= 8 exchange only lane edges through LDS: the lane's
-    // own points stay in registers, neighbours read the first and last three
-    // stage-input points (UE, double-buffered by stage) and the first and last
-    // two fluxes (FE).  Every other case keeps whole lane-interleaved rows.
+    // Full lanes with P >= 8 (EDGE) keep their own points in registers and take
+    // their neighbours' edge values (the last / first three stage-input points,
+    // p and sigma, the last / first two fluxes) across lanes with DPP wavefront
+    // shifts; only lanes 0 and 63 go through small LDS slots (X*) to reach the
+    // adjacent wavefront.  Every other case exchanges whole lane-interleaved
+    // rows.  The forward edge kernel (FWD) holds no rows and keeps the
+    // coefficient tables in LDS instead (LT); the adjoint keeps the rows for its
+    // reverse stencils and reads the tables from global memory.
     static constexpr bool EDGE = FULL && P >= 8;
+    static constexpr bool LT = FWD && EDGE;
+    static constexpr bool ROWS = !LT;
+    static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL + (EDGE ? 2 * NL : 0) : 0)
+                                          + (EDGE ? (size_t)36 * W : 0) + (LT ? (size_t)3 * P * NL : 0) + 4 * W + 8;
 
     double2* U;     // (Phi_s, Pi_s) rows
     double2* F;     // (f1, g) rows; p first / last per lane between B0 and B2
     double* PE;
     double* SE;     // sigma first / last per lane
+    double2* XU;    // EDGE: [2 buffers][W][6] first three / last three points of lanes 0 / 63
+    double* XP;     // EDGE: [W][2] p of the first point of lane 0, of the last point of lane 63
+    double* XS;     // EDGE: [W][2] the same for sigma
+    double2* XF;    // EDGE: [W][4] fluxes of points 0, 1 of lane 0 and P-1, P-2 of lane 63
+    double* T;      // LT: the coefficient tables, [3][P][64 W] as in global memory
     double* red;    // [0,W) delta~ totals, [W,2W) S totals, [2W,3W) flags,
                     // [3W,4W) spare, 4W: p_1, 4W+1: p_{N-2}
     int tid, lane, wv, i0, col, N;
-    int buf;        // UE buffer of the last publish (EDGE)
+    int buf;        // XU buffer of the last publish (EDGE)
     bool has_nm2, near_end, bgauge;
     double h, dt, h24, i12h, kof, thr;
     const ADSCL_GLOBAL double* tab0;
@@ -127,14 +140,37 @@ struct Stage {
     __device__ __forceinline__ void setup(double* lds, const InstConst& ic, const double* tab, int gauge,
                                           double a_collapse)
     {
-        U = reinterpret_cast<double2*>(lds);
-        F = U + SLOTS;
-        // F is free from B0 (its last readers finished the previous stage)
-        // until the flux writes after B2
-        PE = reinterpret_cast<double*>(F);
-        SE = reinterpret_cast<double*>(F + SLOTS);
-        red = SE + 2 * NL;
-        if (EDGE) PE = red + 4 * W + 8;  // no B0 on the edge path: p edges get their own region
+        double* p = lds;
+        U = F = XU = XF = nullptr;
+        PE = SE = XP = XS = T = nullptr;
+        if (ROWS) {
+            U = reinterpret_cast<double2*>(p);
+            F = U + SLOTS;
+            // F is free from B0 (its last readers finished the previous stage)
+            // until the flux writes after B2
+            PE = reinterpret_cast<double*>(F);
+            SE = reinterpret_cast<double*>(F + SLOTS);
+            p = SE + 2 * NL;
+            if (EDGE) {  // no B0 on the edge path: p edges get their own region
+                PE = p;
+                p += 2 * NL;
+            }
+        }
+        if (EDGE) {
+            XU = reinterpret_cast<double2*>(p);
+            p += 24 * W;
+            XP = p;
+            p += 2 * W;
+            XS = p;
+            p += 2 * W;
+            XF = reinterpret_cast<double2*>(p);
+            p += 8 * W;
+        }
+        if (LT) {
+            T = p;
+            p += 3 * P * NL;
+        }
+        red = p;
         buf = 0;
         tid = threadIdx.x;
         lane = tid & 63;
@@ -154,15 +190,20 @@ struct Stage {
         has_nm2 = FULL ? (tid == NL - 1) : ((i0 <= N - 2) && (N - 2 < i0 + P));
         near_end = FULL ? (tid == NL - 1) : ((i0 + P + 2 >= N - 4) && (i0 <= N - 2));
         tab0 = gmem(tab);
+        if constexpr (LT) {
+            // each lane copies exactly the entries it reads later, so no barrier
+#pragma unroll
+            for (int t = 0; t < 3 * P; ++t) T[t * NL + tid] = tab0[t * NL + tid];
+        }
     }
 
-    __device__ __forceinline__ bool own(int k) const { return FULL || (i0 + k <= N - 2); }
+    // Value of v at the lane to the left (tid - 1) / right (tid + 1) within the
+    // wavefront (DPP wave_shr:1 / wave_shl:1); lanes 0 / 63 get 0.  All lanes
+    // must be active.
+    static __device__ __forceinline__ double from_left(double v) { return dpp_d<0x138, 0xf>(v); }
+    static __device__ __forceinline__ double from_right(double v) { return dpp_d<0x130, 0xf>(v); }
 
-    // Edge rows (EDGE): UE buffer b row r (r 0..2: the lane's points 0..2, r 3..5:
-    // points P-1, P-2, P-3) and FE row r (r 0, 1: fluxes of points 0, 1; r 2, 3:
-    // of points P-1, P-2); column l + 1 for lane l, 0 and NL + 1 the ghosts.
-    __device__ __forceinline__ double2* ue(int b, int r) const { return b == 0 ? U + r * RS : F + (2 + r) * RS; }
-    __device__ __forceinline__ double2* fe(int r) const { return r < 2 ? F + r * RS : U + (4 + r) * RS; }
+    __device__ __forceinline__ bool own(int k) const { return FULL || (i0 + k <= N - 2); }
 
     // LDS index of point j, -P <= j < 64 W P + P
     __device__ __forceinline__ int slot(int j) const
@@ -189,6 +230,7 @@ struct Stage {
     // Table t (0 sin x cos x, 1 tan^2 x, 2 cot^2 x) at the lane's point k.
     __device__ __forceinline__ double tab(const TabView& v, int t, int k) const
     {
+        if constexpr (LT) return T[(t * P + k) * NL + tid];
         return *(const ADSCL_GLOBAL double*)(v.base + (v.o + (unsigned)((t * P + k) * NL * 8)));
     }
 
@@ -197,21 +239,17 @@ struct Stage {
     __device__ __forceinline__ void publish(const double* v0, const double* v1)
     {
         if constexpr (EDGE) {
+            // neighbours within the wavefront read the registers; lanes 0 and 63
+            // leave their edge points for the adjacent wavefronts
             buf ^= 1;
+            double2* xu = XU + (buf * W + wv) * 6;
+            if (lane == 0) {
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                ue(buf, r)[col] = make_double2(v0[r], v1[r]);
-                ue(buf, 3 + r)[col] = make_double2(v0[P - 1 - r], v1[P - 1 - r]);
+                for (int r = 0; r < 3; ++r) xu[r] = make_double2(v0[r], v1[r]);
             }
-            if (tid == 0) {
-                ue(buf, 3)[0] = make_double2(-v0[1], v1[1]);
-                ue(buf, 4)[0] = make_double2(-v0[2], v1[2]);
-                ue(buf, 5)[0] = make_double2(-v0[3], v1[3]);
-            }
-            if (tid == NL - 1) {
-                ue(buf, 0)[NL + 1] = make_double2(0.0, 0.0);
-                ue(buf, 1)[NL + 1] = make_double2(v0[P - 1], -v1[P - 1]);
-                ue(buf, 2)[NL + 1] = make_double2(v0[P - 2], -v1[P - 2]);
+            if (lane == 63) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) xu[3 + r] = make_double2(v0[P - 1 - r], v1[P - 1 - r]);
             }
             return;
         }
@@ -257,8 +295,13 @@ struct Stage {
         }
         const double incl = wave_incl_scan(ptot);
         if (lane == 63) red[wv] = incl;
-        PE[tid] = p[0];
-        PE[NL + tid] = p[P - 1];
+        if constexpr (EDGE) {
+            if (lane == 0) XP[2 * wv] = p[0];
+            if (lane == 63) XP[2 * wv + 1] = p[P - 1];
+        } else {
+            PE[tid] = p[0];
+            PE[NL + tid] = p[P - 1];
+        }
         if (tid == 0) red[4 * W] = p[1];
         if (FULL) {
             if (tid == NL - 1) red[4 * W + 1] = p[P - 1];
@@ -276,8 +319,16 @@ struct Stage {
             tot += t;
         }
         const double p1 = red[4 * W], pN2 = red[4 * W + 1];
-        const double pl = (tid > 0) ? PE[NL + tid - 1] : -p1;  // p_{-1} = -p_1
-        const double pr = (tid < NL - 1) ? PE[tid + 1] : 0.0;  // p_{N-1} = 0
+        double pl, pr;
+        if constexpr (EDGE) {
+            pl = from_left(p[P - 1]);
+            pr = from_right(p[0]);
+            if (lane == 0) pl = (wv > 0) ? XP[2 * wv - 1] : -p1;      // p_{-1} = -p_1
+            if (lane == 63) pr = (wv < W - 1) ? XP[2 * wv + 2] : 0.0;  // p_{N-1} = 0
+        } else {
+            pl = (tid > 0) ? PE[NL + tid - 1] : -p1;  // p_{-1} = -p_1
+            pr = (tid < NL - 1) ? PE[tid + 1] : 0.0;  // p_{N-1} = 0
+        }
         dN = -h24 * (24.0 * tot + 2.0 * pN2 + 2.0 * p1);        // delta~_{N-1}
         const double shift = bgauge ? dN : 0.0;
 
@@ -296,8 +347,13 @@ struct Stage {
         }
         const double incl2 = wave_incl_scan(stot);
         if (lane == 63) red[W + wv] = incl2;
-        SE[tid] = sg[0];
-        SE[NL + tid] = sg[P - 1];
+        if constexpr (EDGE) {
+            if (lane == 0) XS[2 * wv] = sg[0];
+            if (lane == 63) XS[2 * wv + 1] = sg[P - 1];
+        } else {
+            SE[tid] = sg[0];
+            SE[NL + tid] = sg[P - 1];
+        }
         __syncthreads();  // B2
         double carry2 = incl2 - stot;
         tot2 = 0.0;
@@ -307,8 +363,16 @@ struct Stage {
             if (v < wv) carry2 += t;
             tot2 += t;
         }
-        const double sl = (tid > 0) ? SE[NL + tid - 1] : sg[1];  // sigma_{-1} = sigma_1
-        const double sr = (tid < NL - 1) ? SE[tid + 1] : 0.0;    // sigma_{N-1} = 0
+        double sl, sr;
+        if constexpr (EDGE) {
+            sl = from_left(sg[P - 1]);
+            sr = from_right(sg[0]);
+            if (lane == 0) sl = (wv > 0) ? XS[2 * wv - 1] : sg[1];     // sigma_{-1} = sigma_1
+            if (lane == 63) sr = (wv < W - 1) ? XS[2 * wv + 2] : 0.0;  // sigma_{N-1} = 0
+        } else {
+            sl = (tid > 0) ? SE[NL + tid - 1] : sg[1];  // sigma_{-1} = sigma_1
+            sr = (tid < NL - 1) ? SE[tid + 1] : 0.0;    // sigma_{N-1} = 0
+        }
         double R2 = carry2;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -519,18 +583,16 @@ struct Stage {
                 chk = fma(E[k], 0.0, chk);
             }
         }
-        fe(0)[col] = make_double2(ff[0], fg[0]);
-        fe(1)[col] = make_double2(ff[1], fg[1]);
-        fe(2)[col] = make_double2(ff[P - 1], fg[P - 1]);
-        fe(3)[col] = make_double2(ff[P - 2], fg[P - 2]);
-        if (tid == 0) {  // f1 even, g odd about x = 0
-            fe(2)[0] = make_double2(ff[1], -fg[1]);
-            fe(3)[0] = make_double2(ff[2], -fg[2]);
-        }
-        if (tid == NL - 1) {
-            // f1_{N-1} = 0, g_{N-1} the even 6th-order extrapolation; ghost N
-            fe(0)[NL + 1] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
-            fe(1)[NL + 1] = make_double2(-ff[P - 1], fg[P - 1]);
+        {
+            double2* xf = XF + wv * 4;
+            if (lane == 0) {
+                xf[0] = make_double2(ff[0], fg[0]);
+                xf[1] = make_double2(ff[1], fg[1]);
+            }
+            if (lane == 63) {
+                xf[2] = make_double2(ff[P - 1], fg[P - 1]);
+                xf[3] = make_double2(ff[P - 2], fg[P - 2]);
+            }
         }
         if (check) {
             if (1.0 < thr) cl = 1;
@@ -549,14 +611,37 @@ struct Stage {
         double ko0[P], ko1[P];
         {
             double2 w[P + 6];  // points i0-3 .. i0+P+2
-            w[0] = ue(buf, 5)[tid];
-            w[1] = ue(buf, 4)[tid];
-            w[2] = ue(buf, 3)[tid];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                w[r] = make_double2(from_left(v0[P - 3 + r]), from_left(v1[P - 3 + r]));
+                w[P + 3 + r] = make_double2(from_right(v0[r]), from_right(v1[r]));
+            }
 #pragma unroll
             for (int k = 0; k < P; ++k) w[3 + k] = make_double2(v0[k], v1[k]);
-            w[P + 3] = ue(buf, 0)[tid + 2];
-            w[P + 4] = ue(buf, 1)[tid + 2];
-            w[P + 5] = ue(buf, 2)[tid + 2];
+            if (lane == 0) {
+                if (wv > 0) {
+                    const double2* xl = XU + (buf * W + wv - 1) * 6;
+                    w[2] = xl[3];
+                    w[1] = xl[4];
+                    w[0] = xl[5];
+                } else {  // Phi odd, Pi even about x = 0
+                    w[2] = make_double2(-v0[1], v1[1]);
+                    w[1] = make_double2(-v0[2], v1[2]);
+                    w[0] = make_double2(-v0[3], v1[3]);
+                }
+            }
+            if (lane == 63) {
+                if (wv < W - 1) {
+                    const double2* xr = XU + (buf * W + wv + 1) * 6;
+                    w[P + 3] = xr[0];
+                    w[P + 4] = xr[1];
+                    w[P + 5] = xr[2];
+                } else {  // Phi = Pi = 0 at pi/2; Phi even, Pi odd about it
+                    w[P + 3] = make_double2(0.0, 0.0);
+                    w[P + 4] = make_double2(v0[P - 1], -v1[P - 1]);
+                    w[P + 5] = make_double2(v0[P - 2], -v1[P - 2]);
+                }
+            }
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 ko0[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
@@ -566,12 +651,32 @@ struct Stage {
             }
         }
         double2 fw[P + 4];  // points i0-2 .. i0+P+1
-        fw[0] = fe(3)[tid];
-        fw[1] = fe(2)[tid];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            fw[r] = make_double2(from_left(ff[P - 2 + r]), from_left(fg[P - 2 + r]));
+            fw[P + 2 + r] = make_double2(from_right(ff[r]), from_right(fg[r]));
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k) fw[2 + k] = make_double2(ff[k], fg[k]);
-        fw[P + 2] = fe(0)[tid + 2];
-        fw[P + 3] = fe(1)[tid + 2];
+        if (lane == 0) {
+            if (wv > 0) {
+                fw[1] = XF[(wv - 1) * 4 + 2];
+                fw[0] = XF[(wv - 1) * 4 + 3];
+            } else {  // f1 even, g odd about x = 0
+                fw[1] = make_double2(ff[1], -fg[1]);
+                fw[0] = make_double2(ff[2], -fg[2]);
+            }
+        }
+        if (lane == 63) {
+            if (wv < W - 1) {
+                fw[P + 2] = XF[(wv + 1) * 4];
+                fw[P + 3] = XF[(wv + 1) * 4 + 1];
+            } else {
+                // f1_{N-1} = 0, g_{N-1} the even 6th-order extrapolation; ghost N
+                fw[P + 2] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
+                fw[P + 3] = make_double2(-ff[P - 1], fg[P - 1]);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const double Df1 = (fw[k].x - 8.0 * fw[k + 1].x + 8.0 * fw[k + 3].x - fw[k + 4].x) * i12h;
