@@ -89,6 +89,7 @@ __device__ __forceinline__ LaneArr<P, NL> lane_arr(ADSCL_GLOBAL double* base, in
     return LaneArr<P, NL>{(ADSCL_GLOBAL char*)base, o};
 }
 
+// LDS of the row layout used by the chunked large-grid kernel.
 template <int P, int W>
 struct StageLayout {
     static constexpr int NL = 64 * W;      // lanes per instance
@@ -106,7 +107,7 @@ struct Stage {
     static constexpr int SLOTS = P * RS;
     static_assert(P >= 4, "lane 0 must own grid points 0..3");
 
-    // Full lanes with P >= 8 (EDGE) keep their own points in registers and take
+    // Full lanes (EDGE: N - 1 = 64 W P) keep their own points in registers and take
     // their neighbours' edge values (the last / first three stage-input points,
     // p and sigma, the last / first two fluxes) across lanes with DPP wavefront
     // shifts; only lanes 0 and 63 go through small LDS slots (X*) to reach the
@@ -114,7 +115,7 @@ struct Stage {
     // rows.  The forward edge kernel (FWD) holds no rows and keeps the
     // coefficient tables in LDS instead (LT); the adjoint keeps the rows for its
     // reverse stencils and reads the tables from global memory.
-    static constexpr bool EDGE = FULL && P >= 8;
+    static constexpr bool EDGE = FULL;
     static constexpr bool LT = FWD && EDGE;
     static constexpr bool ROWS = !LT;
     static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL + (EDGE ? 2 * NL : 0) : 0)
