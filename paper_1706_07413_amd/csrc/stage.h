@@ -118,7 +118,7 @@ struct Stage {
     static constexpr bool EDGE = FULL;
     static constexpr bool LT = FWD && EDGE;
     static constexpr bool ROWS = !LT;
-    static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL + (EDGE ? 2 * NL : 0) : 0)
+    static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL : 0)
                                           + (EDGE ? (size_t)36 * W : 0) + (LT ? (size_t)3 * P * NL : 0) + 4 * W + 8;
 
     double2* U;     // (Phi_s, Pi_s) rows
@@ -148,14 +148,12 @@ struct Stage {
             U = reinterpret_cast<double2*>(p);
             F = U + SLOTS;
             // F is free from B0 (its last readers finished the previous stage)
-            // until the flux writes after B2
+            // until the flux writes after B2 (the edge path keeps its p edges in
+            // XP; the adjoint's reverse writes PE only after a barrier that
+            // follows its last reads of F)
             PE = reinterpret_cast<double*>(F);
             SE = reinterpret_cast<double*>(F + SLOTS);
             p = SE + 2 * NL;
-            if (EDGE) {  // no B0 on the edge path: p edges get their own region
-                PE = p;
-                p += 2 * NL;
-            }
         }
         if (EDGE) {
             XU = reinterpret_cast<double2*>(p);

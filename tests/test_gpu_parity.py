@@ -283,3 +283,25 @@ def test_spectrum_of_snapshot_batches():
     # the current-state call agrees with the last snapshot
     E1, P1, F1 = b.spectrum(J)
     assert np.array_equal(E1, E[-1]) and np.array_equal(P1, P[-1])
+
+
+# every launch configuration the library compiles, full lanes (register/DPP
+# edge exchange, tables in LDS) and ragged grids (row exchange), forced with
+# ADSCL_TUNE at context creation
+TUNED = [(513, 8, 1), (1025, 8, 2), (1025, 16, 1), (2049, 16, 2), (4097, 16, 4), (2049, 4, 8), (4097, 4, 16),
+         (449, 8, 1), (1001, 16, 1), (1901, 16, 2), (3001, 16, 4), (1537, 4, 8), (3333, 4, 16), (777, 8, 2)]
+
+
+@pytest.mark.parametrize("N,P,W", TUNED)
+def test_every_kernel_configuration_matches_oracle(monkeypatch, N, P, W):
+    monkeypatch.setenv("ADSCL_TUNE", "%d:%dx%d" % (N, P, W))
+    n = 120
+    b = adscl.Batch([N], a_collapse=0.02)
+    b.init_gaussian(np.array([6.0]), np.array([0.15]))
+    b.step(n, 1e9)
+    classes, cls = b.kernel_stats()
+    assert (classes[cls[0]]["P"], classes[cls[0]]["W"]) == (P, W)
+    st = gpu_state(b)
+    ref = oracle_gauss(N, 6.0, 0.15, n)
+    assert b.status()["steps"][0] == ref["steps"] == n
+    compare_instance(b, st, 0, ref, "N=%d %dx%d" % (N, P, W))
