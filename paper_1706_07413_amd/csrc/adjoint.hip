@@ -17,8 +17,6 @@
 // it wrote), then runs the four stage adjoints in reverse.
 #include <math.h>
 
-#include <algorithm>
-
 #include "stage.h"
 
 namespace adscl {
@@ -61,8 +59,13 @@ struct Rev {
         for (int k = 0; k < P; ++k) lt += Sb[k];
         const double inc = wave_incl_scan(lt);
         if (lane == 63) red[W + wv] = inc;
-        sg.SE[tid] = Sb[0];
-        sg.SE[NL + tid] = Sb[P - 1];
+        if constexpr (S_t::EDGE) {
+            if (lane == 0) sg.RSb[2 * wv] = Sb[0];
+            if (lane == 63) sg.RSb[2 * wv + 1] = Sb[P - 1];
+        } else {
+            sg.SE[tid] = Sb[0];
+            sg.SE[NL + tid] = Sb[P - 1];
+        }
         __syncthreads();
         double ex = inc - lt, tot = 0.0;
 #pragma unroll
@@ -71,8 +74,16 @@ struct Rev {
             if (v < wv) ex += t;
             tot += t;
         }
-        const double sl = (tid > 0) ? sg.SE[NL + tid - 1] : 0.0;
-        const double sr = (tid < NL - 1) ? sg.SE[tid + 1] : 0.0;
+        double sl, sr;
+        if constexpr (S_t::EDGE) {
+            sl = S_t::from_left(Sb[P - 1]);
+            sr = S_t::from_right(Sb[0]);
+            if (lane == 0) sl = (wv > 0) ? sg.RSb[2 * (wv > 0 ? wv : 1) - 1] : 0.0;
+            if (lane == 63) sr = (wv < W - 1) ? sg.RSb[2 * (wv < W - 1 ? wv : 0) + 2] : 0.0;
+        } else {
+            sl = (tid > 0) ? sg.SE[NL + tid - 1] : 0.0;
+            sr = (tid < NL - 1) ? sg.SE[tid + 1] : 0.0;
+        }
         double qb[P], d[P];
         double lt2 = 0.0, d0 = 0.0;
 #pragma unroll
@@ -100,8 +111,13 @@ struct Rev {
         // suffix sums of d
         const double inc2 = wave_incl_scan(lt2);
         if (lane == 63) red[wv] = inc2;
-        sg.PE[tid] = d[0];
-        sg.PE[NL + tid] = d[P - 1];
+        if constexpr (S_t::EDGE) {
+            if (lane == 0) sg.RDt[2 * wv] = d[0];
+            if (lane == 63) sg.RDt[2 * wv + 1] = d[P - 1];
+        } else {
+            sg.PE[tid] = d[0];
+            sg.PE[NL + tid] = d[P - 1];
+        }
         if (tid == 0) red[4 * W] = d0;
         __syncthreads();
         double ex2 = inc2 - lt2, tot2 = 0.0;
@@ -113,8 +129,16 @@ struct Rev {
         }
         // boundary gauge: shift = dt_{N-1} = -h/24 (24 sum p + 2 p_{N-2} + 2 p_1)
         const double shb = sg.bgauge ? -(tot2 + red[4 * W]) : 0.0;
-        const double dl = (tid > 0) ? sg.PE[NL + tid - 1] : 0.0;
-        const double dr = (tid < NL - 1) ? sg.PE[tid + 1] : 0.0;
+        double dl, dr;
+        if constexpr (S_t::EDGE) {
+            dl = S_t::from_left(d[P - 1]);
+            dr = S_t::from_right(d[0]);
+            if (lane == 0) dl = (wv > 0) ? sg.RDt[2 * (wv > 0 ? wv : 1) - 1] : 0.0;
+            if (lane == 63) dr = (wv < W - 1) ? sg.RDt[2 * (wv < W - 1 ? wv : 0) + 2] : 0.0;
+        } else {
+            dl = (tid > 0) ? sg.PE[NL + tid - 1] : 0.0;
+            dr = (tid < NL - 1) ? sg.PE[tid + 1] : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int j = i0 + k;
@@ -151,74 +175,159 @@ struct Rev {
         double2* U = sg.U;
         double2* F = sg.F;
 
-        __syncthreads();  // last readers of the LDS rows and edges are done
-        // cotangents of the rows: ya (Phi_t rows 1..N-2), yb (Pi_t rows 0..N-2),
-        // yg = cot^2 x yb (rows of D g); every other entry of the rows is 0
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (sg.own(k)) {
-                const double ya = (k == 0 && tid == 0) ? 0.0 : kb0[k];
-                U[k * RS + col] = make_double2(ya, kb1[k]);
-                F[k * RS + col] = make_double2(sg.tab(tb, 2, k) * kb1[k], 0.0);
-            }
-        }
-        const double2 z = make_double2(0.0, 0.0);
-        if (tid == 0) {
-            U[(P - 1) * RS] = z;
-            U[(P - 2) * RS] = z;
-            U[(P - 3) * RS] = z;
-            F[(P - 1) * RS] = z;
-            F[(P - 2) * RS] = z;
-        }
-        if (FULL) {
-            if (tid == NL - 1) {
-                U[0 * RS + NL + 1] = z;
-                U[1 * RS + NL + 1] = z;
-                U[2 * RS + NL + 1] = z;
-                F[0 * RS + NL + 1] = z;
-                F[1 * RS + NL + 1] = z;
-            }
-        } else if (sg.has_nm2) {
-            U[sg.slot(N - 1)] = z;
-            U[sg.slot(N)] = z;
-            U[sg.slot(N + 1)] = z;
-            F[sg.slot(N - 1)] = z;
-            F[sg.slot(N)] = z;
-        }
-        __syncthreads();
-
         double koa[P], kob[P], f1b[P], gb[P];
-        {
-            double2 w[P + 6];  // points i0-3 .. i0+P+2
-#pragma unroll
-            for (int t = 0; t < P + 6; ++t) {
-                const int tt = t - 3;
-                if (tt < 0) w[t] = U[(P + tt) * RS + col - 1];
-                else if (tt < P) w[t] = U[tt * RS + col];
-                else w[t] = U[(tt - P) * RS + col + 1];
-            }
+        if constexpr (S_t::EDGE) {
+            // row cotangents in registers: ya (Phi_t rows 1..N-2), yb = kb1 (Pi_t
+            // rows 0..N-2), yg = cot^2 x yb (rows of D g); the neighbours' by DPP,
+            // the adjacent wavefronts' through RU / RF; ghosts carry zero
+            const int lane = sg.lane, wv = sg.wv;
+            double ya[P], yg[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                // the Kreiss-Oliger stencil is symmetric: its transpose is itself
-                koa[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
-                                + 15.0 * w[k + 4].x - 6.0 * w[k + 5].x + w[k + 6].x);
-                kob[k] = kof * (w[k].y - 6.0 * w[k + 1].y + 15.0 * w[k + 2].y - 20.0 * w[k + 3].y
-                                + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
-                // D is antisymmetric: its transpose is -D
-                f1b[k] = (w[k + 5].x - 8.0 * w[k + 4].x + 8.0 * w[k + 2].x - w[k + 1].x) * i12h;
+                ya[k] = (k == 0 && tid == 0) ? 0.0 : kb0[k];
+                yg[k] = sg.tab(tb, 2, k) * kb1[k];
             }
-        }
-        {
-            double fw[P + 4];  // points i0-2 .. i0+P+1
+            if (lane == 0) {
 #pragma unroll
-            for (int t = 0; t < P + 4; ++t) {
-                const int tt = t - 2;
-                if (tt < 0) fw[t] = F[(P + tt) * RS + col - 1].x;
-                else if (tt < P) fw[t] = F[tt * RS + col].x;
-                else fw[t] = F[(tt - P) * RS + col + 1].x;
+                for (int r = 0; r < 3; ++r) sg.RU[wv * 6 + r] = make_double2(ya[r], kb1[r]);
+                sg.RF[wv * 4] = yg[0];
+                sg.RF[wv * 4 + 1] = yg[1];
             }
+            if (lane == 63) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) gb[k] = (fw[k + 4] - 8.0 * fw[k + 3] + 8.0 * fw[k + 1] - fw[k]) * i12h;
+                for (int r = 0; r < 3; ++r) sg.RU[wv * 6 + 3 + r] = make_double2(ya[P - 1 - r], kb1[P - 1 - r]);
+                sg.RF[wv * 4 + 2] = yg[P - 1];
+                sg.RF[wv * 4 + 3] = yg[P - 2];
+            }
+            __syncthreads();
+            {
+                double2 w[P + 6];  // points i0-3 .. i0+P+2
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    w[r] = make_double2(S_t::from_left(ya[P - 3 + r]), S_t::from_left(kb1[P - 3 + r]));
+                    w[P + 3 + r] = make_double2(S_t::from_right(ya[r]), S_t::from_right(kb1[r]));
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) w[3 + k] = make_double2(ya[k], kb1[k]);
+                const double2 z = make_double2(0.0, 0.0);
+                if (lane == 0) {
+                    const bool in = wv > 0;
+                    const double2* x = sg.RU + (in ? wv - 1 : 0) * 6;
+                    w[2] = in ? x[3] : z;
+                    w[1] = in ? x[4] : z;
+                    w[0] = in ? x[5] : z;
+                }
+                if (lane == 63) {
+                    const bool in = wv < W - 1;
+                    const double2* x = sg.RU + (in ? wv + 1 : 0) * 6;
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) w[P + 3 + r] = in ? x[r] : z;
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    // the Kreiss-Oliger stencil is symmetric: its transpose is itself
+                    koa[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
+                                    + 15.0 * w[k + 4].x - 6.0 * w[k + 5].x + w[k + 6].x);
+                    kob[k] = kof * (w[k].y - 6.0 * w[k + 1].y + 15.0 * w[k + 2].y - 20.0 * w[k + 3].y
+                                    + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
+                    // D is antisymmetric: its transpose is -D
+                    f1b[k] = (w[k + 5].x - 8.0 * w[k + 4].x + 8.0 * w[k + 2].x - w[k + 1].x) * i12h;
+                }
+            }
+            {
+                double fw[P + 4];  // points i0-2 .. i0+P+1
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    fw[r] = S_t::from_left(yg[P - 2 + r]);
+                    fw[P + 2 + r] = S_t::from_right(yg[r]);
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) fw[2 + k] = yg[k];
+                if (lane == 0) {
+                    const bool in = wv > 0;
+                    const double* x = sg.RF + (in ? wv - 1 : 0) * 4;
+                    fw[1] = in ? x[2] : 0.0;
+                    fw[0] = in ? x[3] : 0.0;
+                }
+                if (lane == 63) {
+                    const bool in = wv < W - 1;
+                    const double* x = sg.RF + (in ? wv + 1 : 0) * 4;
+                    fw[P + 2] = in ? x[0] : 0.0;
+                    fw[P + 3] = in ? x[1] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) gb[k] = (fw[k + 4] - 8.0 * fw[k + 3] + 8.0 * fw[k + 1] - fw[k]) * i12h;
+            }
+        } else {
+            __syncthreads();  // last readers of the LDS rows and edges are done
+            // cotangents of the rows: ya (Phi_t rows 1..N-2), yb (Pi_t rows 0..N-2),
+            // yg = cot^2 x yb (rows of D g); every other entry of the rows is 0
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if (sg.own(k)) {
+                    const double ya = (k == 0 && tid == 0) ? 0.0 : kb0[k];
+                    U[k * RS + col] = make_double2(ya, kb1[k]);
+                    F[k * RS + col] = make_double2(sg.tab(tb, 2, k) * kb1[k], 0.0);
+                }
+            }
+            const double2 z = make_double2(0.0, 0.0);
+            if (tid == 0) {
+                U[(P - 1) * RS] = z;
+                U[(P - 2) * RS] = z;
+                U[(P - 3) * RS] = z;
+                F[(P - 1) * RS] = z;
+                F[(P - 2) * RS] = z;
+            }
+            if (FULL) {
+                if (tid == NL - 1) {
+                    U[0 * RS + NL + 1] = z;
+                    U[1 * RS + NL + 1] = z;
+                    U[2 * RS + NL + 1] = z;
+                    F[0 * RS + NL + 1] = z;
+                    F[1 * RS + NL + 1] = z;
+                }
+            } else if (sg.has_nm2) {
+                U[sg.slot(N - 1)] = z;
+                U[sg.slot(N)] = z;
+                U[sg.slot(N + 1)] = z;
+                F[sg.slot(N - 1)] = z;
+                F[sg.slot(N)] = z;
+            }
+            __syncthreads();
+
+            {
+                double2 w[P + 6];  // points i0-3 .. i0+P+2
+#pragma unroll
+                for (int t = 0; t < P + 6; ++t) {
+                    const int tt = t - 3;
+                    if (tt < 0) w[t] = U[(P + tt) * RS + col - 1];
+                    else if (tt < P) w[t] = U[tt * RS + col];
+                    else w[t] = U[(tt - P) * RS + col + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    // the Kreiss-Oliger stencil is symmetric: its transpose is itself
+                    koa[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
+                                    + 15.0 * w[k + 4].x - 6.0 * w[k + 5].x + w[k + 6].x);
+                    kob[k] = kof * (w[k].y - 6.0 * w[k + 1].y + 15.0 * w[k + 2].y - 20.0 * w[k + 3].y
+                                    + 15.0 * w[k + 4].y - 6.0 * w[k + 5].y + w[k + 6].y);
+                    // D is antisymmetric: its transpose is -D
+                    f1b[k] = (w[k + 5].x - 8.0 * w[k + 4].x + 8.0 * w[k + 2].x - w[k + 1].x) * i12h;
+                }
+            }
+            {
+                double fw[P + 4];  // points i0-2 .. i0+P+1
+#pragma unroll
+                for (int t = 0; t < P + 4; ++t) {
+                    const int tt = t - 2;
+                    if (tt < 0) fw[t] = F[(P + tt) * RS + col - 1].x;
+                    else if (tt < P) fw[t] = F[tt * RS + col].x;
+                    else fw[t] = F[(tt - P) * RS + col + 1].x;
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) gb[k] = (fw[k + 4] - 8.0 * fw[k + 3] + 8.0 * fw[k + 1] - fw[k]) * i12h;
+            }
+
         }
         // rows whose stencils reach the ghosts left of x = 0 (Phi odd, Pi even,
         // f1 even, g odd) and the origin row Pi_t(0) = 3 D f2(0) + KO Pi
@@ -239,8 +348,19 @@ struct Rev {
         // rows whose stencils reach past pi/2 (Phi even, Pi odd, f1 odd, g even)
         // and g_{N-1} = (15 g_{N-2} - 6 g_{N-3} + g_{N-4}) / 10
         if (sg.near_end) {
-            const double2 u2 = U[sg.slot(N - 2)], u3 = U[sg.slot(N - 3)];
-            const double yg2 = F[sg.slot(N - 2)].x, yg3 = F[sg.slot(N - 3)].x;
+            double2 u2, u3;
+            double yg2, yg3;
+            if constexpr (S_t::EDGE) {  // the last lane owns N-2 (k = P-1) and N-3
+                u2 = make_double2(kb0[P - 1], kb1[P - 1]);
+                u3 = make_double2(kb0[P - 2], kb1[P - 2]);
+                yg2 = sg.tab(tb, 2, P - 1) * kb1[P - 1];
+                yg3 = sg.tab(tb, 2, P - 2) * kb1[P - 2];
+            } else {
+                u2 = U[sg.slot(N - 2)];
+                u3 = U[sg.slot(N - 3)];
+                yg2 = F[sg.slot(N - 2)].x;
+                yg3 = F[sg.slot(N - 3)].x;
+            }
             const double gN1 = (8.0 * yg2 - yg3) * i12h;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
@@ -296,31 +416,38 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
     const AdjSeg sq = a.sg[b];
     if (!sq.active) return;
     const InstConst ic = a.ic[b];
-    Stage<P, W, FULL> sg;
+    using S_t = Stage<P, W, FULL>;
+    S_t sg;
     sg.setup(lds, ic, a.tab[b], a.gauge, 0.0);
     const int N = sg.N, i0 = sg.i0, tid = sg.tid;
     const double dt = sg.dt;
     ADSCL_GLOBAL double* const stg = gmem(a.stg[b]);
+    // the step's incoming adjoint state U-bar' (fields 0, 1) and the running one
+    // (2, 3): on the edge path in the LDS past the stage's (each lane its own
+    // entries), otherwise in the scratch fields 16..19
+    double* const au = lds + S_t::lds_doubles;
+    auto ub_ld = [&](int f, int k) -> double {
+        if constexpr (S_t::EDGE) return au[(f * P + k) * NL + tid];
+        return lane_arr<P, NL>(stg, tid).ld(16 + f, k);
+    };
+    auto ub_st = [&](int f, int k, double v) {
+        if constexpr (S_t::EDGE) au[(f * P + k) * NL + tid] = v;
+        else lane_arr<P, NL>(stg, tid).st(16 + f, k, v);
+    };
 
-    {
-        const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const bool o = sg.own(k);
-            sv.st(18, k, o ? a.Ubar[ic.off + i0 + k] : 0.0);
-            sv.st(19, k, o ? a.Ubar[a.total + ic.off + i0 + k] : 0.0);
-        }
+    for (int k = 0; k < P; ++k) {
+        const bool o = sg.own(k);
+        ub_st(2, k, o ? a.Ubar[ic.off + i0 + k] : 0.0);
+        ub_st(3, k, o ? a.Ubar[a.total + ic.off + i0 + k] : 0.0);
     }
 
     for (int64_t t = sq.n1 - 1; t >= sq.n0; --t) {
         // the adjoint state at the start of this step's reverse, U-bar'
-        {
-            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                sv.st(16, k, sv.ld(18, k));
-                sv.st(17, k, sv.ld(19, k));
-            }
+        for (int k = 0; k < P; ++k) {
+            ub_st(0, k, ub_ld(2, k));
+            ub_st(1, k, ub_ld(3, k));
         }
         // forward: the stage inputs V_s of step t and their e^-delta and S
         {
@@ -367,13 +494,10 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
         // reverse of U' = U + dt sum_s b_s k_s with stage inputs V_s = U + c_s dt k_{s-1}:
         // kbar_s = dt b_s U-bar' + c_{s+1} dt Vbar_{s+1}, U-bar = U-bar' + sum_s Vbar_s
         double kb0[P], kb1[P];
-        {
-            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                kb0[k] = (dt / 6.0) * sv.ld(16, k);
-                kb1[k] = (dt / 6.0) * sv.ld(17, k);
-            }
+        for (int k = 0; k < P; ++k) {
+            kb0[k] = (dt / 6.0) * ub_ld(0, k);
+            kb1[k] = (dt / 6.0) * ub_ld(1, k);
         }
 #pragma unroll 1
         for (int s = 3; s >= 0; --s) {
@@ -381,24 +505,20 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
             R::stage_reverse(sg, stg, 4 * s, kb0, kb1, vb0, vb1);
             const double cs = (s == 3) ? dt : 0.5 * dt;
             const double bp = (s == 1) ? dt / 6.0 : dt / 3.0;
-            const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                sv.st(18, k, sv.ld(18, k) + vb0[k]);
-                sv.st(19, k, sv.ld(19, k) + vb1[k]);
-                kb0[k] = bp * sv.ld(16, k) + cs * vb0[k];
-                kb1[k] = bp * sv.ld(17, k) + cs * vb1[k];
+                ub_st(2, k, ub_ld(2, k) + vb0[k]);
+                ub_st(3, k, ub_ld(3, k) + vb1[k]);
+                kb0[k] = bp * ub_ld(0, k) + cs * vb0[k];
+                kb1[k] = bp * ub_ld(1, k) + cs * vb1[k];
             }
         }
     }
-    {
-        const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (sg.own(k)) {
-                a.Ubar[ic.off + i0 + k] = sv.ld(18, k);
-                a.Ubar[a.total + ic.off + i0 + k] = sv.ld(19, k);
-            }
+    for (int k = 0; k < P; ++k) {
+        if (sg.own(k)) {
+            a.Ubar[ic.off + i0 + k] = ub_ld(2, k);
+            a.Ubar[a.total + ic.off + i0 + k] = ub_ld(3, k);
         }
     }
 }
@@ -604,43 +724,51 @@ __global__ void gd_tick_kernel(GdState g)
     if (threadIdx.x == 0 && blockIdx.x == 0) g.iter[0] += 1;
 }
 
-template <int P, int W>
-constexpr size_t lds_bytes_for()
+// LDS of the reverse kernel (the stage's, plus the adjoint state on the edge
+// path) and of the end-point kernel
+template <int P, int W, bool FULL>
+constexpr size_t adj_lds_bytes()
 {
-    return std::max(Stage<P, W, true>::lds_doubles, Stage<P, W, false>::lds_doubles) * sizeof(double);
+    using S_t = Stage<P, W, FULL>;
+    return (S_t::lds_doubles + (S_t::EDGE ? (size_t)4 * P * 64 * W : 0)) * sizeof(double);
+}
+
+template <int P, int W, bool FULL>
+constexpr size_t end_lds_bytes()
+{
+    return Stage<P, W, FULL>::lds_doubles * sizeof(double);
 }
 
 template <int P, int W>
 hipError_t launch_adj_t(bool full, int n_blocks, const AdjointArgs& a, hipStream_t s)
 {
-    const size_t lds = lds_bytes_for<P, W>();
     if (full)
-        adjoint_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), lds, s>>>(a);
+        adjoint_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), adj_lds_bytes<P, W, true>(), s>>>(a);
     else
-        adjoint_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), lds, s>>>(a);
+        adjoint_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), adj_lds_bytes<P, W, false>(), s>>>(a);
     return hipGetLastError();
 }
 
 template <int P, int W>
 hipError_t launch_end_t(bool full, int n_blocks, const EndArgs& a, hipStream_t s)
 {
-    const size_t lds = lds_bytes_for<P, W>();
     if (full)
-        endpoint_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), lds, s>>>(a);
+        endpoint_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), end_lds_bytes<P, W, true>(), s>>>(a);
     else
-        endpoint_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), lds, s>>>(a);
+        endpoint_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), end_lds_bytes<P, W, false>(), s>>>(a);
     return hipGetLastError();
 }
 
 template <int P, int W>
 hipError_t prepare_adj_t(size_t max_lds)
 {
-    const int need = (int)lds_bytes_for<P, W>();
-    if ((size_t)need > max_lds) return hipErrorInvalidValue;
     const void* fns[4] = {(const void*)adjoint_kernel<P, W, true>, (const void*)adjoint_kernel<P, W, false>,
                           (const void*)endpoint_kernel<P, W, true>, (const void*)endpoint_kernel<P, W, false>};
-    for (const void* f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need);
+    const size_t need[4] = {adj_lds_bytes<P, W, true>(), adj_lds_bytes<P, W, false>(), end_lds_bytes<P, W, true>(),
+                            end_lds_bytes<P, W, false>()};
+    for (int i = 0; i < 4; ++i) {
+        if (need[i] > max_lds) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)need[i]);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

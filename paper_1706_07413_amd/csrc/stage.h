@@ -110,16 +110,17 @@ struct Stage {
     // Full lanes (EDGE: N - 1 = 64 W P) keep their own points in registers and take
     // their neighbours' edge values (the last / first three stage-input points,
     // p and sigma, the last / first two fluxes) across lanes with DPP wavefront
-    // shifts; only lanes 0 and 63 go through small LDS slots (X*) to reach the
-    // adjacent wavefront.  Every other case exchanges whole lane-interleaved
-    // rows.  The forward edge kernel (FWD) holds no rows and keeps the
-    // coefficient tables in LDS instead (LT); the adjoint keeps the rows for its
-    // reverse stencils and reads the tables from global memory.
+    // shifts; only lanes 0 and 63 go through small LDS slots (X*, and R* for the
+    // adjoint's transposed stencils and reverse scans) to reach the adjacent
+    // wavefront.  Every other case exchanges whole lane-interleaved rows.  The
+    // forward edge kernel (FWD) keeps the coefficient tables in LDS (LT); the
+    // adjoint reads them from global memory and keeps its own state in the LDS
+    // the rows would take.
     static constexpr bool EDGE = FULL;
     static constexpr bool LT = FWD && EDGE;
-    static constexpr bool ROWS = !LT;
+    static constexpr bool ROWS = !EDGE;
     static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL : 0)
-                                          + (EDGE ? (size_t)36 * W : 0) + (LT ? (size_t)3 * P * NL : 0) + 4 * W + 8;
+                                          + (EDGE ? (size_t)56 * W : 0) + (LT ? (size_t)3 * P * NL : 0) + 4 * W + 8;
 
     double2* U;     // (Phi_s, Pi_s) rows
     double2* F;     // (f1, g) rows; p first / last per lane between B0 and B2
@@ -129,6 +130,10 @@ struct Stage {
     double* XP;     // EDGE: [W][2] p of the first point of lane 0, of the last point of lane 63
     double* XS;     // EDGE: [W][2] the same for sigma
     double2* XF;    // EDGE: [W][4] fluxes of points 0, 1 of lane 0 and P-1, P-2 of lane 63
+    double2* RU;    // EDGE, adjoint: [W][6] row cotangents (Phi_t, Pi_t) of points 0..2 of lane 0, P-1..P-3 of lane 63
+    double* RF;     // EDGE, adjoint: [W][4] cotangents of the D g rows, points 0, 1 of lane 0, P-1, P-2 of lane 63
+    double* RSb;    // EDGE, adjoint: [W][2] S-bar of the first point of lane 0, of the last point of lane 63
+    double* RDt;    // EDGE, adjoint: [W][2] the same for the delta~ cotangents
     double* T;      // LT: the coefficient tables, [3][P][64 W] as in global memory
     double* red;    // [0,W) delta~ totals, [W,2W) S totals, [2W,3W) flags,
                     // [3W,4W) spare, 4W: p_1, 4W+1: p_{N-2}
@@ -142,8 +147,8 @@ struct Stage {
                                           double a_collapse)
     {
         double* p = lds;
-        U = F = XU = XF = nullptr;
-        PE = SE = XP = XS = T = nullptr;
+        U = F = XU = XF = RU = nullptr;
+        PE = SE = XP = XS = T = RF = RSb = RDt = nullptr;
         if (ROWS) {
             U = reinterpret_cast<double2*>(p);
             F = U + SLOTS;
@@ -164,6 +169,14 @@ struct Stage {
             p += 2 * W;
             XF = reinterpret_cast<double2*>(p);
             p += 8 * W;
+            RU = reinterpret_cast<double2*>(p);
+            p += 12 * W;
+            RF = p;
+            p += 4 * W;
+            RSb = p;
+            p += 2 * W;
+            RDt = p;
+            p += 2 * W;
         }
         if (LT) {
             T = p;
@@ -322,8 +335,9 @@ struct Stage {
         if constexpr (EDGE) {
             pl = from_left(p[P - 1]);
             pr = from_right(p[0]);
-            if (lane == 0) pl = (wv > 0) ? XP[2 * wv - 1] : -p1;      // p_{-1} = -p_1
-            if (lane == 63) pr = (wv < W - 1) ? XP[2 * wv + 2] : 0.0;  // p_{N-1} = 0
+            // (slot indices clamped so that no lane forms an address outside XP)
+            if (lane == 0) pl = (wv > 0) ? XP[2 * (wv > 0 ? wv : 1) - 1] : -p1;          // p_{-1} = -p_1
+            if (lane == 63) pr = (wv < W - 1) ? XP[2 * (wv < W - 1 ? wv : 0) + 2] : 0.0;  // p_{N-1} = 0
         } else {
             pl = (tid > 0) ? PE[NL + tid - 1] : -p1;  // p_{-1} = -p_1
             pr = (tid < NL - 1) ? PE[tid + 1] : 0.0;  // p_{N-1} = 0
@@ -366,8 +380,8 @@ struct Stage {
         if constexpr (EDGE) {
             sl = from_left(sg[P - 1]);
             sr = from_right(sg[0]);
-            if (lane == 0) sl = (wv > 0) ? XS[2 * wv - 1] : sg[1];     // sigma_{-1} = sigma_1
-            if (lane == 63) sr = (wv < W - 1) ? XS[2 * wv + 2] : 0.0;  // sigma_{N-1} = 0
+            if (lane == 0) sl = (wv > 0) ? XS[2 * (wv > 0 ? wv : 1) - 1] : sg[1];         // sigma_{-1} = sigma_1
+            if (lane == 63) sr = (wv < W - 1) ? XS[2 * (wv < W - 1 ? wv : 0) + 2] : 0.0;  // sigma_{N-1} = 0
         } else {
             sl = (tid > 0) ? SE[NL + tid - 1] : sg[1];  // sigma_{-1} = sigma_1
             sr = (tid < NL - 1) ? SE[tid + 1] : 0.0;    // sigma_{N-1} = 0
