@@ -53,12 +53,15 @@ struct Rev {
         const double h24 = sg.h24;
         double* red = sg.red;
 
-        // suffix sums of Sb
+        // suffix sums of Sb, accumulated from the outer end: the lane's points
+        // from P-1 down, the lanes to its right by doubling steps, the
+        // wavefronts to its right from the last one in (never a total minus a
+        // prefix, which would lose the small suffixes away from the origin)
         double lt = 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) lt += Sb[k];
-        const double inc = wave_incl_scan(lt);
-        if (lane == 63) red[W + wv] = inc;
+        for (int k = P - 1; k >= 0; --k) lt += Sb[k];
+        const double sinc = wave_incl_suffix(lt);
+        if (lane == 0) red[W + wv] = sinc;
         if constexpr (S_t::EDGE) {
             if (lane == 0) sg.RSb[2 * wv] = Sb[0];
             if (lane == 63) sg.RSb[2 * wv + 1] = Sb[P - 1];
@@ -67,12 +70,17 @@ struct Rev {
             sg.SE[NL + tid] = Sb[P - 1];
         }
         __syncthreads();
-        double ex = inc - lt, tot = 0.0;
+        double sufS[P];
+        {
+            double run = S_t::from_right(sinc);  // the lanes right of this one in its wavefront
 #pragma unroll
-        for (int v = 0; v < W; ++v) {
-            const double t = red[W + v];
-            if (v < wv) ex += t;
-            tot += t;
+            for (int v = W - 1; v > 0; --v)
+                if (v > wv) run += red[W + v];
+#pragma unroll
+            for (int k = P - 1; k >= 0; --k) {
+                run += Sb[k];
+                sufS[k] = run;
+            }
         }
         double sl, sr;
         if constexpr (S_t::EDGE) {
@@ -85,11 +93,10 @@ struct Rev {
             sr = (tid < NL - 1) ? sg.SE[tid + 1] : 0.0;
         }
         double qb[P], d[P];
-        double lt2 = 0.0, d0 = 0.0;
+        double d0 = 0.0;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const double suf = tot - ex;
-            ex += Sb[k];
+            const double suf = sufS[k];
             const double sm = (k == 0) ? sl : Sb[k - 1];
             const double sp = (k == P - 1) ? sr : Sb[k + 1];
             const double sb = h24 * (24.0 * suf - 12.0 * Sb[k] + sp - sm);
@@ -106,11 +113,13 @@ struct Rev {
             } else {
                 d[k] = dk;
             }
-            lt2 += d[k];
         }
-        // suffix sums of d
-        const double inc2 = wave_incl_scan(lt2);
-        if (lane == 63) red[wv] = inc2;
+        // suffix sums of d, the same way
+        double lt2 = 0.0;
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) lt2 += d[k];
+        const double sinc2 = wave_incl_suffix(lt2);
+        if (lane == 0) red[wv] = sinc2;
         if constexpr (S_t::EDGE) {
             if (lane == 0) sg.RDt[2 * wv] = d[0];
             if (lane == 63) sg.RDt[2 * wv + 1] = d[P - 1];
@@ -120,12 +129,19 @@ struct Rev {
         }
         if (tid == 0) red[4 * W] = d0;
         __syncthreads();
-        double ex2 = inc2 - lt2, tot2 = 0.0;
+        double sufD[P], tot2 = 0.0;
+        {
+            double run = S_t::from_right(sinc2);
 #pragma unroll
-        for (int v = 0; v < W; ++v) {
-            const double t = red[v];
-            if (v < wv) ex2 += t;
-            tot2 += t;
+            for (int v = W - 1; v >= 0; --v) {
+                if (v > wv) run += red[v];
+                tot2 += red[v];
+            }
+#pragma unroll
+            for (int k = P - 1; k >= 0; --k) {
+                run += d[k];
+                sufD[k] = run;
+            }
         }
         // boundary gauge: shift = dt_{N-1} = -h/24 (24 sum p + 2 p_{N-2} + 2 p_1)
         const double shb = sg.bgauge ? -(tot2 + red[4 * W]) : 0.0;
@@ -142,8 +158,7 @@ struct Rev {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int j = i0 + k;
-            const double suf = tot2 - ex2;
-            ex2 += d[k];
+            const double suf = sufD[k];
             const double dm = (k == 0) ? dl : d[k - 1];
             const double dp = (k == P - 1) ? dr : d[k + 1];
             double pb = -h24 * (24.0 * suf - 12.0 * d[k] + dp - dm);

@@ -63,6 +63,23 @@ __device__ __forceinline__ double wave_incl_scan(double v)
     return v;
 }
 
+// Inclusive suffix sum over the 64 lanes of a wavefront (lane l: the sum over
+// lanes l..63) by doubling steps from higher lanes.  Every partial result is a
+// sum over a run of lanes to the right, so no total is ever subtracted: a
+// suffix keeps its own precision even when the terms left of it are far larger
+// (the adjoint of the constraint solve meets cotangents of order 1/e^-delta at
+// the origin of strong fields).
+__device__ __forceinline__ double wave_incl_suffix(double v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_down(v, d, 64);
+        if (lane + d < 64) v += o;
+    }
+    return v;
+}
+
 // A lane-interleaved global array of doubles, [field][P][64 W]: entry (f, k) of
 // lane l at ((f P + k) 64 W + l).  Held as a uniform base and the lane's byte
 // offset, the latter opaque to the compiler, so that each access is a scalar

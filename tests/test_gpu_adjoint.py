@@ -217,3 +217,50 @@ def test_descend_graph_replays_equal_eager_iterations():
     ce, he, ae = b.descend(eps, c0, 4, 0.2, 4, step0=0.05, ckpt_every=16, eager=True)
     assert np.array_equal(hg, he) and np.array_equal(cg, ce) and np.array_equal(ag, ae)
     assert np.all(np.isfinite(hg))
+
+
+# every launch configuration of the reverse kernel, full lanes (DPP exchange,
+# adjoint state in LDS) and ragged grids (rows, state in the scratch), forced
+# with ADSCL_TUNE at context creation
+TUNED_ADJ = [(257, 4, 1), (513, 4, 2), (1025, 4, 4), (2049, 4, 8), (4097, 4, 16), (513, 8, 1), (1025, 8, 2),
+             (2049, 8, 4), (1025, 16, 1), (2049, 16, 2), (4097, 16, 4), (449, 8, 1), (1901, 16, 2), (3333, 4, 16)]
+
+
+@pytest.mark.parametrize("N,P,W", TUNED_ADJ)
+def test_adjoint_every_kernel_configuration_matches_oracle(monkeypatch, N, P, W):
+    monkeypatch.setenv("ADSCL_TUNE", "%d:%dx%d" % (N, P, W))
+    # 120 steps of eps = 2 data: the drift E_j(t_n) - E_j(0) is at least 1e-3 of
+    # E_j, so L keeps about 11 digits
+    Jc, J, K = 6, 3, 9
+    T = 120 * 0.25 * (math.pi / 2) / (N - 1)
+    eps = np.array([2.0])
+    c = coeffs(5 + N, 1, Jc)
+    b, L, g, v = run_gpu([N], eps, c, J, T, K)
+    classes, cls = b.kernel_stats()
+    assert (classes[cls[0]]["P"], classes[cls[0]]["W"]) == (P, W)
+    ref = O.objective(N, 2.0, c[0], T=T, J=J, K=K)
+    assert v[0] == int(ref["valid"]) == 1
+    assert abs(L[0] - ref["L"]) <= LTOL * ref["L"], (L[0], ref["L"])
+    e = relmax(g[0], ref["grad"])
+    assert e <= GTOL, "N=%d %dx%d: gradient error %.3e" % (N, P, W, e)
+
+
+@pytest.mark.parametrize("N,ns", [(65, 1), (257, 1), (513, 30), (769, 30), (1025, 30), (1537, 30), (2049, 30)])
+def test_adjoint_strong_field_suffix_sums(N, ns):
+    """Mode data at eps = 2 with e^-delta(0) of order 1e-9 (delta(0) = 21): the
+    end-point cotangents of S near the origin are of order 1/e^-delta, so a
+    suffix formed as a total minus a prefix loses about nine digits away from
+    the origin; the reverse scans must sum from the outer end (summed as a total
+    minus a prefix, these cases missed by 2e-7 to 1e-4).  Short windows make the
+    gradient a small difference of the two end points' VJPs; below about 30
+    steps on the larger grids that difference falls under the 1e-9 bar's
+    rounding floor, so those use 30."""
+    Jc, J, K = 6, 3, 9
+    T = ns * 0.25 * (math.pi / 2) / (N - 1)
+    c = coeffs(1030, 1, Jc)
+    print("strong field N", N, "steps", ns, flush=True)
+    _, L, g, v = run_gpu([N], np.array([2.0]), c, J, T, K)
+    ref = O.objective(N, 2.0, c[0], T=T, J=J, K=K)
+    assert v[0] == int(ref["valid"]) == 1
+    e = relmax(g[0], ref["grad"])
+    assert e <= GTOL, "N=%d, %d steps: gradient error %.3e" % (N, ns, e)
