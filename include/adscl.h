@@ -201,6 +201,24 @@ int adscl_sync(adscl_ctx* ctx);
 int adscl_kernel_stats(adscl_ctx* ctx, int32_t max_classes, int32_t* n_classes, int32_t* P, int32_t* W,
                        int32_t* members, double* last_ms, int32_t* cls);
 
+/* Autotuner of the kernel configuration per grid size.  For each of the n
+ * grid sizes n_grid[i] (odd, 17..4097: the one-workgroup range), times every
+ * compiled configuration (P points per lane, W wavefronts) whose lane capacity
+ * 64 W P holds the N - 1 evolved points at the tightest capacity level, on a
+ * batch of 4 instances per compute unit of weak Gaussian data (no collapse)
+ * over `steps` RK4 steps after 8 warm-up steps, and returns the fastest in
+ * P[i], W[i] with its rate in pt-steps/s (host outputs [n], any may be NULL).
+ * apply != 0 records the choices in a process-wide table that every later
+ * adscl_create uses for those grid sizes (ADSCL_TUNE in the environment still
+ * overrides); adscl_autotune_clear empties the table.  Creates and destroys
+ * its own contexts on the current device; synchronous.  Errors: ADSCL_EINVAL
+ * for n < 1, steps < 1, a NULL n_grid or a grid size out of range (checked
+ * before any GPU work); ADSCL_EHIP / ADSCL_ENOMEM from the trials, with the
+ * message from adscl_last_error(NULL). */
+int adscl_autotune(const int32_t* n_grid, int32_t n, int32_t steps, int32_t apply, int32_t* P, int32_t* W,
+                   double* rate);
+void adscl_autotune_clear(void);
+
 /* Packed offsets off_b (host [n_inst]) and the total sum N_b. */
 int adscl_layout(const adscl_ctx* ctx, int64_t* off, int64_t* total);
 

@@ -24,7 +24,8 @@ RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
 # Every function include/adscl.h declares.
 EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
            "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum", "adscl_spectrum_snaps",
-           "adscl_adjoint", "adscl_descend", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error")
+           "adscl_adjoint", "adscl_descend", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error",
+           "adscl_autotune", "adscl_autotune_clear")
 
 
 class AdsclError(RuntimeError):
@@ -78,6 +79,8 @@ def lib():
         "adscl_layout": (ctypes.c_int, [_vp, _vp, _vp]),
         "adscl_kernel_stats": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
         "adscl_last_error": (ctypes.c_char_p, [_vp]),
+        "adscl_autotune": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
+        "adscl_autotune_clear": (None, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -85,6 +88,28 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
+
+
+def autotune(n_grid, steps=256, apply=True):
+    """Time every compiled kernel configuration for each grid size on a full
+    batch of weak data and return {N: (P, W, pt-steps/s)} of the fastest; with
+    ``apply`` the choices hold for every later Batch in this process (see
+    adscl_autotune in include/adscl.h)."""
+    L = lib()
+    Ns = np.ascontiguousarray(np.asarray(n_grid, dtype=np.int32))
+    n = len(Ns)
+    P, W = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    rate = np.zeros(n)
+    rc = L.adscl_autotune(Ns.ctypes.data, n, int(steps), 1 if apply else 0, P.ctypes.data, W.ctypes.data,
+                          rate.ctypes.data)
+    if rc:
+        raise AdsclError(rc, L.adscl_last_error(None).decode())
+    return {int(Ns[i]): (int(P[i]), int(W[i]), float(rate[i])) for i in range(n)}
+
+
+def autotune_clear():
+    """Forget the autotuner's choices (later Batches use the default rule)."""
+    lib().adscl_autotune_clear()
 
 
 def _ptr_mem(a):

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -108,10 +109,22 @@ int fail(adscl_ctx* c, int code, const std::string& msg)
                         std::string(#call) + ": " + hipGetErrorString(e_));                       \
     } while (0)
 
-// Kernel configuration for grid size N: the smallest lane capacity 64 W P that
-// holds the N-1 evolved points, taking P = 8 over W = 8 at 2048 points (four
-// wavefronts, one per SIMD, so that two instances can share a compute unit).
-// ADSCL_TUNE="N:PxW,..." overrides per N.
+// Configurations chosen by adscl_autotune (grid size -> configuration), and the
+// one a tuning trial forces on the calling thread.
+std::mutex g_tune_mu;
+std::map<int, ClassCfg> g_tuned;
+thread_local int g_force_N = 0;
+thread_local ClassCfg g_force{0, 0};
+
+// Every configuration the kernels are compiled for.
+const ClassCfg kAllClasses[] = {{4, 1}, {4, 2}, {4, 4},  {4, 8},  {4, 16}, {8, 1},
+                                {8, 2}, {8, 4}, {8, 8}, {16, 1}, {16, 2}, {16, 4}};
+
+// Kernel configuration for grid size N: ADSCL_TUNE="N:PxW,..." if it names one
+// for N, else the configuration a tuning trial forces, else the autotuner's
+// choice for N, else the smallest lane capacity 64 W P that holds the N-1
+// evolved points, taking P = 8 over W = 8 at 2048 points (four wavefronts, one
+// per SIMD, so that two instances can share a compute unit).
 ClassCfg choose_class(int N)
 {
     if (const char* t = std::getenv("ADSCL_TUNE")) {
@@ -127,6 +140,12 @@ ClassCfg choose_class(int N)
             }
             pos = end + 1;
         }
+    }
+    if (g_force_N == N) return g_force;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(N);
+        if (it != g_tuned.end()) return it->second;
     }
     static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {8, 8}};
     for (const ClassCfg& c : pref)
@@ -701,6 +720,52 @@ int stage_inputs(adscl_ctx* c, const double* eps, const double* coef, int32_t Jc
     *d_eps = (double*)e;
     *d_c = (double*)k;
     return ADSCL_OK;
+}
+
+// One tuning trial: a batch of `n_inst` instances of grid size N in
+// configuration cfg, weak Gaussian data, `steps` RK4 steps after 8 warm-up
+// steps; the rate in pt-steps/s, or a negative adscl error code.
+double tune_trial(int N, ClassCfg cfg, int n_inst, int steps, std::string& err)
+{
+    g_force_N = N;
+    g_force = cfg;
+    std::vector<int32_t> grid(n_inst, N);
+    adscl_config c;
+    c.n_inst = n_inst;
+    c.n_grid = grid.data();
+    c.cfl = 0.25;
+    c.ko_sigma = 0.5;
+    c.a_collapse = 0.0;
+    c.gauge = ADSCL_GAUGE_BOUNDARY;
+    c.n_modes = 1;
+    c.flags = 0;
+    adscl_ctx* ctx = nullptr;
+    int rc = adscl_create(&c, nullptr, &ctx);
+    g_force_N = 0;
+    if (rc) {
+        err = adscl_last_error(nullptr);
+        return rc;
+    }
+    std::vector<double> eps(n_inst, 1e-3), sig(n_inst, 0.2);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    float ms = 0.0f;
+    double rate = 0.0;
+    if ((rc = adscl_init_gaussian(ctx, eps.data(), sig.data(), ADSCL_MEM_HOST)) == 0 &&
+        (rc = adscl_step(ctx, 8, 1e300, 0, 0, nullptr, ADSCL_MEM_DEVICE)) == 0 && (rc = adscl_sync(ctx)) == 0) {
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess ||
+            hipEventRecord(t0, ctx->stream) != hipSuccess)
+            rc = ADSCL_EHIP;
+        if (!rc) rc = adscl_step(ctx, steps, 1e300, 0, 0, nullptr, ADSCL_MEM_DEVICE);
+        if (!rc && (hipEventRecord(t1, ctx->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, t0, t1) != hipSuccess))
+            rc = ADSCL_EHIP;
+        if (!rc) rate = (double)n_inst * N * steps / (ms * 1e-3);
+    }
+    if (rc) err = adscl_last_error(ctx) ? adscl_last_error(ctx) : "tuning trial failed";
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    adscl_destroy(ctx);
+    return rc ? (double)rc : rate;
 }
 
 }  // namespace
@@ -1288,6 +1353,61 @@ int adscl_layout(const adscl_ctx* c, int64_t* off, int64_t* total)
     if (off) std::memcpy(off, c->off.data(), sizeof(int64_t) * c->n_inst);
     if (total) *total = c->total;
     return ADSCL_OK;
+}
+
+int adscl_autotune(const int32_t* n_grid, int32_t n, int32_t steps, int32_t apply, int32_t* P, int32_t* W,
+                   double* rate)
+{
+    if (!n_grid || n < 1) return fail(nullptr, ADSCL_EINVAL, "autotune: n_grid is NULL or n < 1");
+    if (steps < 1) return fail(nullptr, ADSCL_EINVAL, "autotune: steps < 1");
+    for (int i = 0; i < n; ++i) {
+        const int N = n_grid[i];
+        if (N < 17 || N > kMaxOneGroup || (N % 2) == 0)
+            return fail(nullptr, ADSCL_EINVAL,
+                        "autotune: N=" + std::to_string(N) + " (need odd N, 17 <= N <= 4097)");
+    }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return fail(nullptr, ADSCL_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    const int n_inst = 4 * std::max(cus, 1);
+    for (int i = 0; i < n; ++i) {
+        const int N = n_grid[i];
+        // the tightest capacity level that holds the grid
+        int cap = 0;
+        for (const ClassCfg& c : kAllClasses) {
+            const int k = 64 * c.W * c.P;
+            if (k >= N - 1 && (cap == 0 || k < cap)) cap = k;
+        }
+        ClassCfg best{0, 0};
+        double best_rate = -1.0;
+        std::string err;
+        for (const ClassCfg& c : kAllClasses) {
+            if (64 * c.W * c.P != cap) continue;
+            const double r = tune_trial(N, c, n_inst, steps, err);
+            if (r > best_rate) {
+                best_rate = r;
+                best = c;
+            }
+        }
+        if (best_rate <= 0.0)
+            return fail(nullptr, (int)best_rate < 0 ? (int)best_rate : ADSCL_EHIP, "autotune N=" +
+                        std::to_string(N) + ": no configuration ran (" + err + ")");
+        if (P) P[i] = best.P;
+        if (W) W[i] = best.W;
+        if (rate) rate[i] = best_rate;
+        if (apply) {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tuned[N] = best;
+        }
+    }
+    return ADSCL_OK;
+}
+
+void adscl_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned.clear();
 }
 
 const char* adscl_last_error(const adscl_ctx* c)

@@ -81,3 +81,13 @@ def test_create_accepts_large_grids_before_touching_the_gpu():
     assert rc != adscl.EINVAL, L.adscl_last_error(None)
     if rc == adscl.OK:
         L.adscl_destroy(h)
+
+
+@pytest.mark.parametrize("n_grid,n,steps", [([1025], 0, 8), ([1025], 1, 0), ([1024], 1, 8), ([4099], 1, 8),
+                                            ([15], 1, 8), ([513, 16385], 2, 8)])
+def test_autotune_rejects_bad_arguments_before_touching_the_gpu(n_grid, n, steps):
+    L = adscl.lib()
+    N = np.asarray(n_grid, np.int32)
+    assert L.adscl_autotune(N.ctypes.data, n, steps, 0, None, None, None) == adscl.EINVAL
+    assert L.adscl_autotune(None, 1, 8, 0, None, None, None) == adscl.EINVAL
+    L.adscl_autotune_clear()
