@@ -146,6 +146,61 @@ def large_instance_rate(adscl, steps=4096):
             "steps_per_s": steps / dt}
 
 
+def config1_full(adscl, chunk=65536):
+    """The whole 16385-point two-mode run of the paper's production resolution:
+    0.05 (e_0 + 0.6 e_1), boundary time, to t = 200 (8 344 303 RK4 steps), with
+    (Phi, Pi, A, delta, m) stored every 1024 steps and the 64-mode energy
+    spectrum of every stored state by the FP64 MFMA projection (8150 spectra,
+    in batches of 512 states).  Progress goes to stderr, one line per chunk."""
+    import torch
+    from paper_1706_07413_amd import inputs as I
+    cfg = I.config1()
+    N = int(cfg["N"][0])
+    J, every = int(cfg["n_modes"]), int(cfg["spec_every"])
+    b = adscl.Batch(cfg["N"], gauge=cfg["gauge"], a_collapse=cfg["a_collapse"], n_modes=J)
+    b.init_modes(cfg["eps"], np.ascontiguousarray(cfg["c"]))
+    dt = 0.25 * (math.pi / 2) / (N - 1)
+    n_final = int(math.ceil(cfg["T"] / dt - 1e-9))
+    slots = n_final // every + 1
+    snaps = torch.zeros((slots, 5, N), dtype=torch.float64, device="cuda")
+    con0 = b.constraints()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < n_final:
+        b.step(chunk, cfg["T"], snap_every=every, snaps=snaps)
+        st = b.status()
+        steps = int(st["steps"][0])
+        print("config1: step %d of %d, t = %.3f, %.1f s, state %d" % (steps, n_final, st["t"][0],
+              time.perf_counter() - t0, int(st["state"][0])), file=sys.stderr, flush=True)
+        if st["state"][0] not in (adscl.RUNNING, adscl.DONE):
+            break
+    torch.cuda.synchronize()
+    t_evolve = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    E = torch.empty((slots, J), dtype=torch.float64, device="cuda")
+    for s0 in range(0, slots, 512):
+        e, _, _ = b.spectrum_snaps(J, snaps[s0:s0 + 512])
+        E[s0:s0 + e.shape[0]] = e[:, 0, :]
+    torch.cuda.synchronize()
+    t_spec = time.perf_counter() - t1
+    E = E.cpu().numpy()
+    con1 = b.constraints()[0]
+    st = b.status()
+    if os.path.isdir("gpurun_out"):
+        np.save(os.path.join("gpurun_out", "config1_spectra.npy"), E)
+    tot = E.sum(axis=1)
+    return {"workload": "single_twomode_N16385 to t=200, spectra of 64 modes every %d steps" % every,
+            "steps": int(st["steps"][0]), "state": int(st["state"][0]), "t": float(st["t"][0]),
+            "evolve_s": t_evolve, "pt_steps_per_s": N * int(st["steps"][0]) / t_evolve,
+            "us_per_step": t_evolve / max(int(st["steps"][0]), 1) * 1e6,
+            "spectra": slots, "spectra_s": t_spec,
+            "E0_E1_first": [float(E[0, 0]), float(E[0, 1])], "E0_E1_last": [float(E[-1, 0]), float(E[-1, 1])],
+            "sum_E_first_last": [float(tot[0]), float(tot[-1])],
+            "max_mode_with_1e-12_of_energy_last": int(np.max(np.nonzero(E[-1] > 1e-12 * tot[-1])[0])),
+            "constraints_t0": [float(x) for x in con0], "constraints_end": [float(x) for x in con1]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +213,8 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient-rate leg")
     ap.add_argument("--adjoint-t", type=float, default=1.0, help="time window of the adjoint leg")
+    ap.add_argument("--config1-full", action="store_true",
+                    help="run only the whole 16385-point t=200 run with its spectra (about 11 minutes)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint leg and print its result (for profiling it)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -191,6 +248,9 @@ def main():
     tuned = adscl.autotune(sorted(set(int(n) for n in cfg["N"]) | {2049, 4097}), steps=256, apply=True)
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_rate(adscl, args.adjoint_t)}))
+        return
+    if args.config1_full:
+        print(json.dumps({"config1_full": config1_full(adscl)}))
         return
     T = args.t_end
     eps = torch.tensor(cfg["eps"], dtype=torch.float64, device="cuda")
