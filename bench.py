@@ -146,6 +146,26 @@ def large_instance_rate(adscl, steps=4096):
             "steps_per_s": steps / dt}
 
 
+def paper_table_rates(adscl, steps=2048):
+    """The single-instance workloads of the paper's speed tables, on this GPU:
+    the dynamic metric at N = 32769 and the frozen metric (A = 1, delta = 0,
+    the linear wave) at N = 65537, two-mode data 0.05 (e_0 + 0.6 e_1), a window
+    of `steps` RK4 steps after 64 warm-up steps."""
+    out = {}
+    for name, N, flags in (("dynamic_N32769", 32769, 0), ("frozen_N65537", 65537, adscl.FROZEN_METRIC)):
+        b = adscl.Batch([N], a_collapse=0.01, n_modes=2, flags=flags)
+        b.init_modes(np.array([0.05]), np.array([[1.0, 0.6]]))
+        b.step(64, 1e9)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(steps, 1e9)
+        b.sync()
+        dt = time.perf_counter() - t0
+        b.close()
+        out[name] = {"pt_steps_per_s": N * steps / dt, "us_per_step": dt / steps * 1e6, "steps": steps}
+    return out
+
+
 def config1_full(adscl, chunk=65536):
     """The whole 16385-point two-mode run of the paper's production resolution:
     0.05 (e_0 + 0.6 e_1), boundary time, to t = 200 (8 344 303 RK4 steps), with
@@ -328,6 +348,7 @@ def main():
                                   "batched_over_single": value / (work / args.steps / t_single)}
     if not args.no_single:
         out["large_instance"] = large_instance_rate(adscl)
+        out["paper_tables"] = paper_table_rates(adscl)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_rate(adscl, args.adjoint_t)
     if not args.no_cpu_baseline:

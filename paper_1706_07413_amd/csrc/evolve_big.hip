@@ -64,7 +64,7 @@ struct Chunk {
     double* SE;
     double* red;   // as the single-workgroup kernel, plus [4W+8, 4W+8+3G) per-chunk factors
     int tid, lane, wv, g, G, a, i0, col, N;
-    bool first, last, has_nm2, near_end, bgauge;
+    bool first, last, has_nm2, near_end, bgauge, frozen;
     double h24, i12h, kof, thr;
     const ADSCL_GLOBAL double* tabI;  // tables of the whole instance, [g][3][P][NL]
     const ADSCL_GLOBAL double* tab0;  // this chunk's
@@ -210,122 +210,133 @@ struct Chunk {
                 q[k] = own(k) ? w[k + 3].x * w[k + 3].x + w[k + 3].y * w[k + 3].y : 0.0;
             }
         }
-        // local prefix sums of p and sigma'
-        double p[P];
-        double ptot = 0.0;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            p[k] = tab(tb, 0, k) * q[k];
-            ptot += p[k];
-        }
-        const double incl = wave_incl_scan(ptot);
-        if (lane == 63) red[wv] = incl;
-        PE[tid] = p[0];
-        PE[NL + tid] = p[P - 1];
-        if (first && tid == 0) red[4 * W] = p[1];
-        if (has_nm2) {
-#pragma unroll
-            for (int k = 0; k < P; ++k)
-                if (i0 + k == N - 2) red[4 * W + 1] = p[k];
-        }
-        __syncthreads();  // B1
-        double carry = incl - ptot, tot = 0.0;
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-            const double t = red[v];
-            if (v < wv) carry += t;
-            tot += t;
-        }
-        double pl, pr;
-        if (tid > 0) {
-            pl = PE[NL + tid - 1];
-        } else if (first) {
-            pl = -red[4 * W];
-        } else {
-            const double2 u = U[(P - 1) * RS];  // point a - 1
-            pl = tab_at(0, a - 1) * (u.x * u.x + u.y * u.y);
-        }
-        if (tid < NL - 1) {
-            pr = PE[tid + 1];
-        } else if (last) {
-            pr = 0.0;
-        } else {
-            const double2 u = U[NL + 1];  // point a + C
-            pr = tab_at(0, a + C) * (u.x * u.x + u.y * u.y);
-        }
-        double sg[P], dp[P], E[P];
-        double R = carry, stot = 0.0;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            R += p[k];
-            const double pm = (k == 0) ? pl : p[k - 1];
-            const double pp = (k == P - 1) ? pr : p[k + 1];
-            dp[k] = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp);
-            E[k] = exp(-dp[k]);
-            sg[k] = tab(tb, 1, k) * q[k] * E[k];
-            stot += sg[k];
-        }
-        const double incl2 = wave_incl_scan(stot);
-        if (lane == 63) red[W + wv] = incl2;
-        SE[tid] = sg[0];
-        SE[NL + tid] = sg[P - 1];
-        __syncthreads();  // B2
-        double carry2 = incl2 - stot, tot2 = 0.0;
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-            const double t = red[W + v];
-            if (v < wv) carry2 += t;
-            tot2 += t;
-        }
-        // sync B: chunk totals and edge values
-        if (tid == 0) {
-            double* r = rec(g);
-            r[XS_P] = tot;
-            r[XS_S] = tot2;
-            r[XS_SF] = sg[0];
-            if (first) r[XS_P1] = red[4 * W];
-            if (last) r[XS_PN] = red[4 * W + 1];
-        }
-        if (tid == NL - 1 && !last) rec(g)[XS_SL] = sg[P - 1];
-        if (!grid_sync()) return -1;
-        // per-chunk factors F_h and the sigma carry D_g
-        double* fac = red + 4 * W + 8;  // [0,G) F_h, [G,2G) F_h * (sigma' total of h)
-        {
-            const double p1 = rec(0)[XS_P1];
-            double tp = 0.0;
-            for (int c = 0; c < G; ++c) tp += rec(c)[XS_P];
-            const double pN2 = rec(G - 1)[XS_PN];
-            const double dN = -h24 * (24.0 * tp + 2.0 * pN2 + 2.0 * p1);
-            const double shift = bgauge ? dN : 0.0;
-            if (tid < G) {
-                double Cg = 0.0;
-                for (int c = 0; c < tid; ++c) Cg += rec(c)[XS_P];
-                const double Fh = exp(24.0 * h24 * Cg + 2.0 * h24 * p1 + shift);
-                fac[tid] = Fh;
-                fac[G + tid] = Fh * rec(tid)[XS_S];
-            }
-            if (tid == 0) red[4 * W + 2] = dN;
-        }
-        __syncthreads();
-        const double Fg = fac[g];
-        double Dg = 0.0;
-        for (int c = 0; c < g; ++c) Dg += fac[G + c];
-        const double sl = (tid > 0) ? SE[NL + tid - 1]
-                                    : (first ? sg[1] : rec(g - 1)[XS_SL] * fac[g - 1] / Fg);
-        const double sr = (tid < NL - 1) ? SE[tid + 1] : (last ? 0.0 : rec(g + 1)[XS_SF] * fac[g + 1] / Fg);
-        double S[P];
-        {
-            double R2 = carry2;
+        // the constraint solve: two scans over the grid (skipped, uniformly for
+        // every chunk, with the metric frozen: A = 1, delta = 0)
+        double E[P], S[P];
+        double dN = 0.0;
+        if (frozen) {
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                R2 += sg[k];
-                const double sm = (k == 0) ? sl : sg[k - 1];
-                const double sp = (k == P - 1) ? sr : sg[k + 1];
-                S[k] = h24 * (24.0 * (Dg + Fg * R2) + Fg * (-12.0 * sg[k] + sm - sp));
-                E[k] *= Fg;
+                E[k] = 1.0;
+                S[k] = 0.0;
             }
+        } else {
+            // local prefix sums of p and sigma'
+            double p[P];
+            double ptot = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                p[k] = tab(tb, 0, k) * q[k];
+                ptot += p[k];
+            }
+            const double incl = wave_incl_scan(ptot);
+            if (lane == 63) red[wv] = incl;
+            PE[tid] = p[0];
+            PE[NL + tid] = p[P - 1];
+            if (first && tid == 0) red[4 * W] = p[1];
+            if (has_nm2) {
+#pragma unroll
+                for (int k = 0; k < P; ++k)
+                    if (i0 + k == N - 2) red[4 * W + 1] = p[k];
+            }
+            __syncthreads();  // B1
+            double carry = incl - ptot, tot = 0.0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) {
+                const double t = red[v];
+                if (v < wv) carry += t;
+                tot += t;
+            }
+            double pl, pr;
+            if (tid > 0) {
+                pl = PE[NL + tid - 1];
+            } else if (first) {
+                pl = -red[4 * W];
+            } else {
+                const double2 u = U[(P - 1) * RS];  // point a - 1
+                pl = tab_at(0, a - 1) * (u.x * u.x + u.y * u.y);
+            }
+            if (tid < NL - 1) {
+                pr = PE[tid + 1];
+            } else if (last) {
+                pr = 0.0;
+            } else {
+                const double2 u = U[NL + 1];  // point a + C
+                pr = tab_at(0, a + C) * (u.x * u.x + u.y * u.y);
+            }
+            double sg[P], dp[P];
+            double R = carry, stot = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                R += p[k];
+                const double pm = (k == 0) ? pl : p[k - 1];
+                const double pp = (k == P - 1) ? pr : p[k + 1];
+                dp[k] = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp);
+                E[k] = exp(-dp[k]);
+                sg[k] = tab(tb, 1, k) * q[k] * E[k];
+                stot += sg[k];
+            }
+            const double incl2 = wave_incl_scan(stot);
+            if (lane == 63) red[W + wv] = incl2;
+            SE[tid] = sg[0];
+            SE[NL + tid] = sg[P - 1];
+            __syncthreads();  // B2
+            double carry2 = incl2 - stot, tot2 = 0.0;
+#pragma unroll
+            for (int v = 0; v < W; ++v) {
+                const double t = red[W + v];
+                if (v < wv) carry2 += t;
+                tot2 += t;
+            }
+            // sync B: chunk totals and edge values
+            if (tid == 0) {
+                double* r = rec(g);
+                r[XS_P] = tot;
+                r[XS_S] = tot2;
+                r[XS_SF] = sg[0];
+                if (first) r[XS_P1] = red[4 * W];
+                if (last) r[XS_PN] = red[4 * W + 1];
+            }
+            if (tid == NL - 1 && !last) rec(g)[XS_SL] = sg[P - 1];
+            if (!grid_sync()) return -1;
+            // per-chunk factors F_h and the sigma carry D_g
+            double* fac = red + 4 * W + 8;  // [0,G) F_h, [G,2G) F_h * (sigma' total of h)
+            {
+                const double p1 = rec(0)[XS_P1];
+                double tp = 0.0;
+                for (int c = 0; c < G; ++c) tp += rec(c)[XS_P];
+                const double pN2 = rec(G - 1)[XS_PN];
+                const double dN = -h24 * (24.0 * tp + 2.0 * pN2 + 2.0 * p1);
+                const double shift = bgauge ? dN : 0.0;
+                if (tid < G) {
+                    double Cg = 0.0;
+                    for (int c = 0; c < tid; ++c) Cg += rec(c)[XS_P];
+                    const double Fh = exp(24.0 * h24 * Cg + 2.0 * h24 * p1 + shift);
+                    fac[tid] = Fh;
+                    fac[G + tid] = Fh * rec(tid)[XS_S];
+                }
+                if (tid == 0) red[4 * W + 2] = dN;
+            }
+            __syncthreads();
+            const double Fg = fac[g];
+            double Dg = 0.0;
+            for (int c = 0; c < g; ++c) Dg += fac[G + c];
+            const double sl = (tid > 0) ? SE[NL + tid - 1]
+                                        : (first ? sg[1] : rec(g - 1)[XS_SL] * fac[g - 1] / Fg);
+            const double sr = (tid < NL - 1) ? SE[tid + 1] : (last ? 0.0 : rec(g + 1)[XS_SF] * fac[g + 1] / Fg);
+            {
+                double R2 = carry2;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    R2 += sg[k];
+                    const double sm = (k == 0) ? sl : sg[k - 1];
+                    const double sp = (k == P - 1) ? sr : sg[k + 1];
+                    S[k] = h24 * (24.0 * (Dg + Fg * R2) + Fg * (-12.0 * sg[k] + sm - sp));
+                    E[k] *= Fg;
+                }
+            }
+            dN = red[4 * W + 2];
         }
-        const double dN = red[4 * W + 2];
 
         // fluxes
         double f2_1 = 0.0, f2_2 = 0.0, chk = 0.0;
@@ -474,6 +485,7 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.has_nm2 = cs.last && (cs.i0 <= N - 2) && (N - 2 < cs.i0 + P);
     cs.near_end = cs.last && (cs.i0 + P + 2 >= N - 4) && (cs.i0 <= N - 2);
     cs.bgauge = a.gauge == 0;
+    cs.frozen = a.frozen != 0;
     cs.h24 = ic.h24;
     cs.i12h = ic.i12h;
     cs.kof = ic.kof;

@@ -96,3 +96,23 @@ def test_large_instance_equals_itself_alone_and_chunked_calls():
     g1 = gpu_state(b1)
     for f in FIELDS:
         assert np.array_equal(b.split(g[f])[0], g1[f]), f
+
+
+@pytest.mark.parametrize("Ns,n", [([16385, 129], 120), ([65537], 24)])
+def test_frozen_metric_on_chunked_grids(Ns, n):
+    """The frozen-metric mode (A = 1, delta = 0: the linear wave of the paper's
+    fixed-metric benchmark) on grids split over several workgroups, up to the
+    largest supported N, beside a one-workgroup instance."""
+    c = np.array([[1.0, -0.5, 0.25, 0.1]] * len(Ns))
+    print("frozen chunked", Ns, n, flush=True)
+    b = adscl.Batch(Ns, n_modes=4, flags=adscl.FROZEN_METRIC)
+    b.init_modes(np.full(len(Ns), 0.3), c)
+    b.step(n, 1e9)
+    st = gpu_state(b)
+    for i, N in enumerate(Ns):
+        Phi, Pi = O.init_modes(N, 0.3, c[i])
+        ref = O.evolve(Phi, Pi, n, frozen=True)
+        for f in ("Phi", "Pi"):
+            assert_close(b.split(st[f])[i], ref[f], "frozen N=%d %s" % (N, f))
+        assert np.all(b.split(st["A"])[i] == 1.0)
+        assert np.all(b.split(st["delta"])[i] == 0.0)
