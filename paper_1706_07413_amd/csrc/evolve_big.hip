@@ -63,6 +63,7 @@ struct Chunk {
     double* PE;
     double* SE;
     double* red;   // as the single-workgroup kernel, plus [4W+8, 4W+8+3G) per-chunk factors
+    double* T;     // this chunk's coefficient tables, [3][P][NL], copied into LDS at launch
     int tid, lane, wv, g, G, a, i0, col, N;
     bool first, last, has_nm2, near_end, bgauge, frozen;
     double h24, i12h, kof, thr;
@@ -90,9 +91,9 @@ struct Chunk {
         asm volatile("" : "+v"(o));
         return TabView{(const ADSCL_GLOBAL char*)tab0, o};
     }
-    __device__ __forceinline__ double tab(const TabView& v, int t, int k) const
+    __device__ __forceinline__ double tab(const TabView&, int t, int k) const
     {
-        return *(const ADSCL_GLOBAL double*)(v.base + (v.o + (unsigned)((t * P + k) * NL * 8)));
+        return T[(t * P + k) * NL + tid];
     }
     // table t at global point j of any chunk
     __device__ __forceinline__ double tab_at(int t, int j) const
@@ -103,15 +104,22 @@ struct Chunk {
 
     // Grid-wide barrier over the instance's G workgroups.  Returns false when
     // the wait ran out (or another workgroup's did): the caller leaves.
+    // Every wavefront first waits for its own stores (the exchange records) to
+    // complete, so that after the workgroup barrier one thread's device-scope
+    // release (an L2 write-back) covers the whole workgroup; that thread counts
+    // in, polls the counter with relaxed loads (an acquiring poll would
+    // invalidate L2 on every iteration), acquires once, and the closing barrier
+    // passes the acquisition on.
     __device__ __forceinline__ bool grid_sync()
     {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         target += (unsigned long long)G;
         if (tid == 0) {
-            __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             unsigned long long n = 0;
-            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++n > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -119,9 +127,9 @@ struct Chunk {
                 }
             }
             red[4 * W + 7] = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1.0 : 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         return red[4 * W + 7] == 0.0;
     }
 
@@ -455,6 +463,13 @@ struct Chunk {
     }
 };
 
+// LDS of a chunk: rows, sigma edges, reductions, per-chunk factors, tables
+template <int P, int W>
+constexpr size_t big_lds_bytes_for()
+{
+    return (StageLayout<P, W>::lds_doubles + (size_t)3 * 64 + (size_t)3 * P * 64 * W) * sizeof(double);
+}
+
 template <int P, int W>
 __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArgs x)
 {
@@ -492,6 +507,10 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.thr = a.a_collapse;
     cs.tabI = gmem(a.tab[b]);
     cs.tab0 = cs.tabI + (size_t)cs.g * 3 * Ch::C;
+    // each lane copies exactly the table entries it reads later: no barrier
+    cs.T = cs.red + 4 * W + 8 + 3 * 64;
+#pragma unroll
+    for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
     cs.xg = x.xch;
     cs.ctr = x.ctr;
     cs.err = x.err;
@@ -595,7 +614,7 @@ hipError_t launch_big_t(int chunks, const EvolveArgs& a, const BigArgs& x, hipSt
     big_reset_kernel<<<dim3(1), dim3(64), 0, s>>>(x.ctr, x.err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = StageLayout<P, W>::lds_doubles * sizeof(double) + (size_t)(3 * 64) * sizeof(double);
+    const size_t lds = big_lds_bytes_for<P, W>();
     EvolveArgs ea = a;
     BigArgs xa = x;
     void* args[] = {(void*)&ea, (void*)&xa};
@@ -605,7 +624,7 @@ hipError_t launch_big_t(int chunks, const EvolveArgs& a, const BigArgs& x, hipSt
 template <int P, int W>
 hipError_t prepare_big_t(size_t max_lds)
 {
-    const size_t need = StageLayout<P, W>::lds_doubles * sizeof(double) + (size_t)(3 * 64) * sizeof(double);
+    const size_t need = big_lds_bytes_for<P, W>();
     if (need > max_lds) return hipErrorInvalidValue;
     return hipFuncSetAttribute((const void*)evolve_big_kernel<P, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)need);
@@ -628,7 +647,8 @@ bool big_class_supported(ClassCfg c)
 
 size_t big_lds_bytes(ClassCfg c)
 {
-    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * 64) * sizeof(double);
+    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * 64 + 3 * c.P * 64 * c.W) *
+           sizeof(double);
 }
 
 hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds)
