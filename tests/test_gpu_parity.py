@@ -305,3 +305,24 @@ def test_every_kernel_configuration_matches_oracle(monkeypatch, N, P, W):
     ref = oracle_gauss(N, 6.0, 0.15, n)
     assert b.status()["steps"][0] == ref["steps"] == n
     compare_instance(b, st, 0, ref, "N=%d %dx%d" % (N, P, W))
+
+
+def test_qp_family_temperatures_match_the_paper():
+    """The paper's approximate QP families (tests/golden: k_d, mu and the printed
+    temperature) as one batch: mode-sum data at eps = 1e-6, the constraint solve
+    at t = 0 and the MFMA projection; the temperature sum E_j / sum E_j / omega_j
+    must round to the printed value and agree with the oracle's."""
+    from test_oracle_pins import family_coefficients, qp_family_rows, temperature
+    rows = qp_family_rows()
+    N, J = 1025, 40
+    c = np.stack([family_coefficients(kd, mu, J) for kd, mu, _, _ in rows])
+    b = adscl.Batch([N] * len(rows), n_modes=J)
+    b.init_modes(np.full(len(rows), 1e-6), np.ascontiguousarray(c))
+    E, _, _ = b.spectrum(J)
+    for i, (kd, mu, T, dec) in enumerate(rows):
+        Tg = temperature(E[i])
+        assert abs(Tg - T) <= 0.5 * 10.0 ** (-dec), (kd, mu, Tg, T)
+        Phi, Pi = O.init_modes(N, 1e-6, c[i])
+        r = O.evolve(Phi, Pi, 0)
+        Eo, _, _ = O.spectrum(Phi, Pi, r["A"], J)
+        assert abs(Tg - temperature(Eo)) <= 1e-12 * temperature(Eo)

@@ -9,6 +9,7 @@ Eqs. (4)-(6), the boundary/regularity conditions Eqs. (7)-(12), and the
 collapse/non-finite criteria.  None of these needs a GPU.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -432,3 +433,36 @@ def test_spectrum_parseval_and_linear_limit():
         A = O.constraints(Phi, Pi)["A"]
         E, Ph, _ = O.spectrum(Phi, Pi, A, 4)
         assert np.max(np.abs(E / (eps ** 2 * c ** 2) - 1)) < 5 * eps ** 2
+
+
+def qp_family_rows():
+    rows = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "qp_family_temperatures.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            kd, mu, T, dec = line.split()
+            rows.append((int(kd), float(mu), float(T), int(dec)))
+    return rows
+
+
+def family_coefficients(kd, mu, J):
+    """Pi(x,0) = sum_k omega_k A_k e_k(x) with A_k = exp(-mu |k - k_d|) (eps applied separately)."""
+    k = np.arange(J)
+    return (3.0 + 2.0 * k) * np.exp(-mu * np.abs(k - kd))
+
+
+def temperature(E):
+    w = 3.0 + 2.0 * np.arange(len(E))
+    return float(np.sum(E) / np.sum(E / w))
+
+
+@pytest.mark.parametrize("kd,mu,T,dec", qp_family_rows())
+def test_qp_family_temperature_matches_the_paper(kd, mu, T, dec):
+    """The paper's printed temperatures of its approximate QP families (tests/golden),
+    through the oracle's mode sum, constraint solve at t = 0 and projection, in the
+    linear regime (eps = 1e-6, A = 1 to 1e-12)."""
+    N, J = 1025, 40
+    Phi, Pi = O.init_modes(N, 1e-6, family_coefficients(kd, mu, J))
+    r = O.evolve(Phi, Pi, 0)
+    E, _, _ = O.spectrum(Phi, Pi, r["A"], J)
+    assert abs(temperature(E) - T) <= 0.5 * 10.0 ** (-dec), (kd, mu, temperature(E), T)
