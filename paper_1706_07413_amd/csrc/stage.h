@@ -49,6 +49,25 @@ __device__ __forceinline__ double dpp_d(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// DPP move of a double where lanes without a source lane keep `old`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_old(double old, double v)
+{
+    const long long o = __double_as_longlong(old), b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Double of lane `l` (wavefront-uniform) broadcast to every lane.
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Inclusive prefix sum over the 64 lanes of a wavefront: shifts by 1, 2, 4, 8
 // within rows of 16 lanes, then the row totals through the row broadcasts of
 // lanes 15 and 31 (gfx9 DPP row_shr / row_bcast).
@@ -137,16 +156,21 @@ struct Stage {
     static constexpr bool LT = FWD && EDGE;
     static constexpr bool ROWS = !EDGE;
     static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL : 0)
-                                          + (EDGE ? (size_t)56 * W : 0) + (LT ? (size_t)3 * P * NL : 0) + 4 * W + 8;
+                                          + (EDGE ? (size_t)36 * (W + 2) + 20 * W : 0) + (LT ? (size_t)3 * P * NL : 0)
+                                          + 4 * W + 8;
 
     double2* U;     // (Phi_s, Pi_s) rows
     double2* F;     // (f1, g) rows; p first / last per lane between B0 and B2
     double* PE;
     double* SE;     // sigma first / last per lane
-    double2* XU;    // EDGE: [2 buffers][W][6] first three / last three points of lanes 0 / 63
-    double* XP;     // EDGE: [W][2] p of the first point of lane 0, of the last point of lane 63
-    double* XS;     // EDGE: [W][2] the same for sigma
-    double2* XF;    // EDGE: [W][4] fluxes of points 0, 1 of lane 0 and P-1, P-2 of lane 63
+    // EDGE slots, one per wavefront (slot wv + 1) plus two ghost slots: slot 0
+    // holds the parity images left of x = 0 as if a wavefront -1 had written
+    // them, slot W + 1 the end point and its images past pi/2, so that every
+    // wavefront reads its two neighbours' slots the same way
+    double2* XU;    // [2 buffers][W+2][6] points 0..2 of lane 0, then P-1..P-3 of lane 63
+    double* XP;     // [W+2][2] p of the first point of lane 0, of the last point of lane 63
+    double* XS;     // [W+2][2] the same for sigma
+    double2* XF;    // [W+2][4] fluxes of points 0, 1 of lane 0 and P-1, P-2 of lane 63
     double2* RU;    // EDGE, adjoint: [W][6] row cotangents (Phi_t, Pi_t) of points 0..2 of lane 0, P-1..P-3 of lane 63
     double* RF;     // EDGE, adjoint: [W][4] cotangents of the D g rows, points 0, 1 of lane 0, P-1, P-2 of lane 63
     double* RSb;    // EDGE, adjoint: [W][2] S-bar of the first point of lane 0, of the last point of lane 63
@@ -179,13 +203,13 @@ struct Stage {
         }
         if (EDGE) {
             XU = reinterpret_cast<double2*>(p);
-            p += 24 * W;
+            p += 24 * (W + 2);
             XP = p;
-            p += 2 * W;
+            p += 2 * (W + 2);
             XS = p;
-            p += 2 * W;
+            p += 2 * (W + 2);
             XF = reinterpret_cast<double2*>(p);
-            p += 8 * W;
+            p += 8 * (W + 2);
             RU = reinterpret_cast<double2*>(p);
             p += 12 * W;
             RF = p;
@@ -271,7 +295,7 @@ struct Stage {
             // neighbours within the wavefront read the registers; lanes 0 and 63
             // leave their edge points for the adjacent wavefronts
             buf ^= 1;
-            double2* xu = XU + (buf * W + wv) * 6;
+            double2* xu = XU + (buf * (W + 2) + wv + 1) * 6;
             if (lane == 0) {
 #pragma unroll
                 for (int r = 0; r < 3; ++r) xu[r] = make_double2(v0[r], v1[r]);
@@ -279,6 +303,17 @@ struct Stage {
             if (lane == 63) {
 #pragma unroll
                 for (int r = 0; r < 3; ++r) xu[3 + r] = make_double2(v0[P - 1 - r], v1[P - 1 - r]);
+            }
+            if (tid == 0) {  // Phi odd, Pi even about x = 0: points -1, -2, -3
+                double2* g = XU + buf * (W + 2) * 6;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) g[3 + r] = make_double2(-v0[1 + r], v1[1 + r]);
+            }
+            if (tid == NL - 1) {  // Phi = Pi = 0 at pi/2; Phi even, Pi odd about it: points N-1, N, N+1
+                double2* g = XU + (buf * (W + 2) + W + 1) * 6;
+                g[0] = make_double2(0.0, 0.0);
+                g[1] = make_double2(v0[P - 1], -v1[P - 1]);
+                g[2] = make_double2(v0[P - 2], -v1[P - 2]);
             }
             return;
         }
@@ -307,6 +342,23 @@ struct Stage {
         }
     }
 
+    // Sums of the wavefront totals r[0..W): over the wavefronts before this one
+    // (`before`) and over all (`all`).  Lanes v < W hold r[v], a DPP prefix
+    // runs over them (W <= 16: within the first row of 16 lanes), and two
+    // wavefront-uniform lane reads broadcast the results, instead of every lane
+    // adding all W totals under a mask.
+    __device__ __forceinline__ void wave_totals(const double* r, double& before, double& all) const
+    {
+        double x = (lane < W) ? r[lane < W ? lane : 0] : 0.0;
+        if constexpr (W > 1) x += dpp_d<0x111, 0xf>(x);  // row_shr:1
+        if constexpr (W > 2) x += dpp_d<0x112, 0xf>(x);  // row_shr:2
+        if constexpr (W > 4) x += dpp_d<0x114, 0xf>(x);  // row_shr:4
+        if constexpr (W > 8) x += dpp_d<0x118, 0xf>(x);  // row_shr:8
+        all = readlane_d(x, W - 1);
+        const int w = __builtin_amdgcn_readfirstlane(wv);
+        before = (w > 0) ? readlane_d(x, w > 0 ? w - 1 : 0) : 0.0;
+    }
+
     // Constraint solve of the published state given q = Phi^2 + Pi^2 of the own
     // points (Eqs. (5)-(6)): delta (gauge applied), e^{-delta} and S at own
     // points, the delta~ end value dN and the S total tot2.  Contains barriers
@@ -325,8 +377,10 @@ struct Stage {
         const double incl = wave_incl_scan(ptot);
         if (lane == 63) red[wv] = incl;
         if constexpr (EDGE) {
-            if (lane == 0) XP[2 * wv] = p[0];
-            if (lane == 63) XP[2 * wv + 1] = p[P - 1];
+            if (lane == 0) XP[2 * (wv + 1)] = p[0];
+            if (lane == 63) XP[2 * (wv + 1) + 1] = p[P - 1];
+            if (tid == 0) XP[1] = -p[1];                // p_{-1} = -p_1
+            if (tid == NL - 1) XP[2 * (W + 1)] = 0.0;  // p_{N-1} = 0
         } else {
             PE[tid] = p[0];
             PE[NL + tid] = p[P - 1];
@@ -340,21 +394,15 @@ struct Stage {
                 if (i0 + k == N - 2) red[4 * W + 1] = p[k];
         }
         __syncthreads();  // B1
-        double carry = incl - ptot, tot = 0.0;
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-            const double t = red[v];
-            if (v < wv) carry += t;
-            tot += t;
-        }
+        double carry, tot;
+        wave_totals(red, carry, tot);
+        carry += incl - ptot;
         const double p1 = red[4 * W], pN2 = red[4 * W + 1];
         double pl, pr;
         if constexpr (EDGE) {
-            pl = from_left(p[P - 1]);
-            pr = from_right(p[0]);
-            // (slot indices clamped so that no lane forms an address outside XP)
-            if (lane == 0) pl = (wv > 0) ? XP[2 * (wv > 0 ? wv : 1) - 1] : -p1;          // p_{-1} = -p_1
-            if (lane == 63) pr = (wv < W - 1) ? XP[2 * (wv < W - 1 ? wv : 0) + 2] : 0.0;  // p_{N-1} = 0
+            // lanes 0 / 63 take the neighbouring wavefront's (or the ghost) slot
+            pl = dpp_old<0x138>(XP[2 * wv + 1], p[P - 1]);
+            pr = dpp_old<0x130>(XP[2 * (wv + 2)], p[0]);
         } else {
             pl = (tid > 0) ? PE[NL + tid - 1] : -p1;  // p_{-1} = -p_1
             pr = (tid < NL - 1) ? PE[tid + 1] : 0.0;  // p_{N-1} = 0
@@ -378,27 +426,22 @@ struct Stage {
         const double incl2 = wave_incl_scan(stot);
         if (lane == 63) red[W + wv] = incl2;
         if constexpr (EDGE) {
-            if (lane == 0) XS[2 * wv] = sg[0];
-            if (lane == 63) XS[2 * wv + 1] = sg[P - 1];
+            if (lane == 0) XS[2 * (wv + 1)] = sg[0];
+            if (lane == 63) XS[2 * (wv + 1) + 1] = sg[P - 1];
+            if (tid == 0) XS[1] = sg[1];                // sigma_{-1} = sigma_1
+            if (tid == NL - 1) XS[2 * (W + 1)] = 0.0;  // sigma_{N-1} = 0
         } else {
             SE[tid] = sg[0];
             SE[NL + tid] = sg[P - 1];
         }
         __syncthreads();  // B2
-        double carry2 = incl2 - stot;
-        tot2 = 0.0;
-#pragma unroll
-        for (int v = 0; v < W; ++v) {
-            const double t = red[W + v];
-            if (v < wv) carry2 += t;
-            tot2 += t;
-        }
+        double carry2;
+        wave_totals(red + W, carry2, tot2);
+        carry2 += incl2 - stot;
         double sl, sr;
         if constexpr (EDGE) {
-            sl = from_left(sg[P - 1]);
-            sr = from_right(sg[0]);
-            if (lane == 0) sl = (wv > 0) ? XS[2 * (wv > 0 ? wv : 1) - 1] : sg[1];         // sigma_{-1} = sigma_1
-            if (lane == 63) sr = (wv < W - 1) ? XS[2 * (wv < W - 1 ? wv : 0) + 2] : 0.0;  // sigma_{N-1} = 0
+            sl = dpp_old<0x138>(XS[2 * wv + 1], sg[P - 1]);
+            sr = dpp_old<0x130>(XS[2 * (wv + 2)], sg[0]);
         } else {
             sl = (tid > 0) ? SE[NL + tid - 1] : sg[1];  // sigma_{-1} = sigma_1
             sr = (tid < NL - 1) ? SE[tid + 1] : 0.0;    // sigma_{N-1} = 0
@@ -614,7 +657,7 @@ struct Stage {
             }
         }
         {
-            double2* xf = XF + wv * 4;
+            double2* xf = XF + (wv + 1) * 4;
             if (lane == 0) {
                 xf[0] = make_double2(ff[0], fg[0]);
                 xf[1] = make_double2(ff[1], fg[1]);
@@ -622,6 +665,15 @@ struct Stage {
             if (lane == 63) {
                 xf[2] = make_double2(ff[P - 1], fg[P - 1]);
                 xf[3] = make_double2(ff[P - 2], fg[P - 2]);
+            }
+            if (tid == 0) {  // f1 even, g odd about x = 0: points -1, -2
+                XF[2] = make_double2(ff[1], -fg[1]);
+                XF[3] = make_double2(ff[2], -fg[2]);
+            }
+            if (tid == NL - 1) {
+                // f1_{N-1} = 0, g_{N-1} the even 6th-order extrapolation; ghost N
+                XF[(W + 1) * 4] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
+                XF[(W + 1) * 4 + 1] = make_double2(-ff[P - 1], fg[P - 1]);
             }
         }
         if (check) {
@@ -641,37 +693,19 @@ struct Stage {
         double ko0[P], ko1[P];
         {
             double2 w[P + 6];  // points i0-3 .. i0+P+2
+            {
+                // lanes 0 / 63 take the neighbouring wavefront's (or the ghost) slot
+                const double2* xl = XU + (buf * (W + 2) + wv) * 6;
+                const double2* xr = XU + (buf * (W + 2) + wv + 2) * 6;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                w[r] = make_double2(from_left(v0[P - 3 + r]), from_left(v1[P - 3 + r]));
-                w[P + 3 + r] = make_double2(from_right(v0[r]), from_right(v1[r]));
+                for (int r = 0; r < 3; ++r) {
+                    const double2 gl = xl[5 - r], gr = xr[r];
+                    w[r] = make_double2(dpp_old<0x138>(gl.x, v0[P - 3 + r]), dpp_old<0x138>(gl.y, v1[P - 3 + r]));
+                    w[P + 3 + r] = make_double2(dpp_old<0x130>(gr.x, v0[r]), dpp_old<0x130>(gr.y, v1[r]));
+                }
             }
 #pragma unroll
             for (int k = 0; k < P; ++k) w[3 + k] = make_double2(v0[k], v1[k]);
-            if (lane == 0) {
-                if (wv > 0) {
-                    const double2* xl = XU + (buf * W + wv - 1) * 6;
-                    w[2] = xl[3];
-                    w[1] = xl[4];
-                    w[0] = xl[5];
-                } else {  // Phi odd, Pi even about x = 0
-                    w[2] = make_double2(-v0[1], v1[1]);
-                    w[1] = make_double2(-v0[2], v1[2]);
-                    w[0] = make_double2(-v0[3], v1[3]);
-                }
-            }
-            if (lane == 63) {
-                if (wv < W - 1) {
-                    const double2* xr = XU + (buf * W + wv + 1) * 6;
-                    w[P + 3] = xr[0];
-                    w[P + 4] = xr[1];
-                    w[P + 5] = xr[2];
-                } else {  // Phi = Pi = 0 at pi/2; Phi even, Pi odd about it
-                    w[P + 3] = make_double2(0.0, 0.0);
-                    w[P + 4] = make_double2(v0[P - 1], -v1[P - 1]);
-                    w[P + 5] = make_double2(v0[P - 2], -v1[P - 2]);
-                }
-            }
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 ko0[k] = kof * (w[k].x - 6.0 * w[k + 1].x + 15.0 * w[k + 2].x - 20.0 * w[k + 3].x
@@ -681,32 +715,18 @@ struct Stage {
             }
         }
         double2 fw[P + 4];  // points i0-2 .. i0+P+1
+        {
+            const double2* xl = XF + wv * 4;
+            const double2* xr = XF + (wv + 2) * 4;
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            fw[r] = make_double2(from_left(ff[P - 2 + r]), from_left(fg[P - 2 + r]));
-            fw[P + 2 + r] = make_double2(from_right(ff[r]), from_right(fg[r]));
+            for (int r = 0; r < 2; ++r) {
+                const double2 gl = xl[3 - r], gr = xr[r];
+                fw[r] = make_double2(dpp_old<0x138>(gl.x, ff[P - 2 + r]), dpp_old<0x138>(gl.y, fg[P - 2 + r]));
+                fw[P + 2 + r] = make_double2(dpp_old<0x130>(gr.x, ff[r]), dpp_old<0x130>(gr.y, fg[r]));
+            }
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) fw[2 + k] = make_double2(ff[k], fg[k]);
-        if (lane == 0) {
-            if (wv > 0) {
-                fw[1] = XF[(wv - 1) * 4 + 2];
-                fw[0] = XF[(wv - 1) * 4 + 3];
-            } else {  // f1 even, g odd about x = 0
-                fw[1] = make_double2(ff[1], -fg[1]);
-                fw[0] = make_double2(ff[2], -fg[2]);
-            }
-        }
-        if (lane == 63) {
-            if (wv < W - 1) {
-                fw[P + 2] = XF[(wv + 1) * 4];
-                fw[P + 3] = XF[(wv + 1) * 4 + 1];
-            } else {
-                // f1_{N-1} = 0, g_{N-1} the even 6th-order extrapolation; ghost N
-                fw[P + 2] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
-                fw[P + 3] = make_double2(-ff[P - 1], fg[P - 1]);
-            }
-        }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const double Df1 = (fw[k].x - 8.0 * fw[k + 1].x + 8.0 * fw[k + 3].x - fw[k + 4].x) * i12h;
