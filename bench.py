@@ -27,7 +27,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "FP64 grid-point RK4 updates/s, batched vs single-instance; adjoint grads/s"
 UNIT = "grid-point RK4 updates/s"
-# Algorithmic work per grid point per RK4 stage of the scheme (see DESIGN.md):
+# Algorithmic work per grid point per RK4 stage of the scheme:
 # 76 FP64 add/mul/fma-terms of the constraint scans, fluxes, D and KO stencils
 # and RK combination, plus one exp counted at 24 flops.
 FLOP_PER_PT_STAGE = 100.0
@@ -252,8 +252,8 @@ def main():
         print(json.dumps({"copy_bytes": n * 8, "dispatches": 3}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: every box here has a single MI355X and the batch is not "
-              "sharded across GPUs (instances are independent; see DESIGN.md for the sharding plan).",
+        print("bench.py measures one GPU only: the instances are independent, and a run on several "
+              "GPUs would shard the batch by instance, which this benchmark does not do.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -39,13 +39,16 @@ __device__ __forceinline__ ADSCL_GLOBAL T* gmem(T* p)
 }
 
 // DPP move of a double: both 32-bit halves through the same data-parallel
-// primitive (lanes without a source read 0).
+// primitive (lanes without a source read 0).  With every row enabled the
+// zero comes from the bound control, so no destination has to be cleared
+// first; a partial row mask keeps the old value (0) in the masked rows.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_d(double v)
 {
+    constexpr bool bc = ROW_MASK == 0xf;
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, bc);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, bc);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -57,6 +60,32 @@ __device__ __forceinline__ double dpp_old(double old, double v)
     const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// e^x by Tang's table-driven method (P. T. P. Tang, ACM Trans. Math. Softw. 15
+// (1989) 144-157): x = (64 m + j) ln 2/64 + r with |r| <= ln 2/128, so that
+// e^x = 2^m 2^(j/64) e^r.  r is formed against a two-part ln 2/64 (the second
+// part holds the bits the first drops), e^r - 1 is its degree-5 Taylor
+// polynomial (truncation below r^6/720 < 4e-17), and the 64 values 2^(j/64)
+// come from a table (t64, in LDS).  Arguments below -746 are raised to -746
+// (e^x is 0 in double there), and so is a NaN (the constraint solve tests q,
+// e^-delta and delta~_{N-1} for finiteness itself); up to x = 2.3e7 the result
+// is e^x within 1.3 ulp, overflowing to +inf through the exponent m, and past
+// that it is not finite.
+__device__ __forceinline__ double exp_tab(double x, const double* t64)
+{
+    x = __builtin_fmax(x, -746.0);
+    const double n = __builtin_rint(x * 0x1.71547652b82fep+6);  // 64/ln 2
+    double r = __builtin_fma(-n, 0x1.62e42fefa39efp-7, x);       // ln 2/64, leading part
+    r = __builtin_fma(-n, 0x1.abc9e3b39803fp-62, r);             // and the rest
+    const int ni = (int)n;
+    double e = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    e = __builtin_fma(r, e, 1.0 / 6.0);
+    e = __builtin_fma(r, e, 0.5);
+    e = __builtin_fma(r, e, 1.0);
+    e *= r;  // e^r - 1
+    const double t = t64[ni & 63];
+    return __builtin_ldexp(__builtin_fma(t, e, t), ni >> 6);
 }
 
 // Double of lane `l` (wavefront-uniform) broadcast to every lane.
@@ -157,7 +186,7 @@ struct Stage {
     static constexpr bool ROWS = !EDGE;
     static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL : 0)
                                           + (EDGE ? (size_t)36 * (W + 2) + 20 * W : 0) + (LT ? (size_t)3 * P * NL : 0)
-                                          + 4 * W + 8;
+                                          + 4 * W + 8 + 64;
 
     double2* U;     // (Phi_s, Pi_s) rows
     double2* F;     // (f1, g) rows; p first / last per lane between B0 and B2
@@ -178,6 +207,7 @@ struct Stage {
     double* T;      // LT: the coefficient tables, [3][P][64 W] as in global memory
     double* red;    // [0,W) delta~ totals, [W,2W) S totals, [2W,3W) flags,
                     // [3W,4W) spare, 4W: p_1, 4W+1: p_{N-2}
+    double* X64;    // 2^(j/64), j = 0..63, the table of exp_tab
     int tid, lane, wv, i0, col, N;
     int buf;        // XU buffer of the last publish (EDGE)
     bool has_nm2, near_end, bgauge;
@@ -224,8 +254,11 @@ struct Stage {
             p += 3 * P * NL;
         }
         red = p;
+        X64 = red + 4 * W + 8;
         buf = 0;
         tid = threadIdx.x;
+        // read only after the barrier of the first constraint solve
+        if (tid < 64) X64[tid] = exp2((double)tid * (1.0 / 64.0));
         lane = tid & 63;
         wv = tid >> 6;
         N = ic.N;
@@ -419,7 +452,7 @@ struct Stage {
             const double pp = (k == P - 1) ? pr : p[k + 1];
             const double dtil = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp + 2.0 * p1);
             dl[k] = dtil - shift;
-            E[k] = exp(-dl[k]);
+            E[k] = exp_tab(-dl[k], X64);
             sg[k] = tab(tb, 1, k) * q[k] * E[k];  // table is 0 off 1..N-2
             stot += sg[k];
         }
