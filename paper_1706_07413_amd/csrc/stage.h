@@ -112,20 +112,25 @@ __device__ __forceinline__ double wave_incl_scan(double v)
 }
 
 // Inclusive suffix sum over the 64 lanes of a wavefront (lane l: the sum over
-// lanes l..63) by doubling steps from higher lanes.  Every partial result is a
-// sum over a run of lanes to the right, so no total is ever subtracted: a
-// suffix keeps its own precision even when the terms left of it are far larger
-// (the adjoint of the constraint solve meets cotangents of order 1/e^-delta at
-// the origin of strong fields).
+// lanes l..63): shifts from higher lanes by 1, 2, 4, 8 within rows of 16 lanes
+// (DPP row_shl; lanes past a row's end read 0), then the totals of the rows to
+// the right, the outermost first, read from each row's first lane.  Every
+// partial result is a sum over a run of lanes to the right, so no total is ever
+// subtracted: a suffix keeps its own precision even when the terms left of it
+// are far larger (the adjoint of the constraint solve meets cotangents of order
+// 1/e^-delta at the origin of strong fields).
 __device__ __forceinline__ double wave_incl_suffix(double v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double o = __shfl_down(v, d, 64);
-        if (lane + d < 64) v += o;
-    }
-    return v;
+    v += dpp_d<0x101, 0xf>(v);  // row_shl:1
+    v += dpp_d<0x102, 0xf>(v);  // row_shl:2
+    v += dpp_d<0x104, 0xf>(v);  // row_shl:4
+    v += dpp_d<0x108, 0xf>(v);  // row_shl:8
+    const int row = (threadIdx.x & 63) >> 4;
+    const double t3 = readlane_d(v, 48), t2 = readlane_d(v, 32), t1 = readlane_d(v, 16);
+    double right = (row < 3) ? t3 : 0.0;
+    if (row < 2) right += t2;
+    if (row < 1) right += t1;
+    return v + right;
 }
 
 // A lane-interleaved global array of doubles, [field][P][64 W]: entry (f, k) of
