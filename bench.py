@@ -166,12 +166,13 @@ def paper_table_rates(adscl, steps=2048):
     return out
 
 
-def config1_full(adscl, chunk=65536):
+def config1_full(adscl, chunk=65536, spectra_out=None):
     """The whole 16385-point two-mode run of the paper's production resolution:
     0.05 (e_0 + 0.6 e_1), boundary time, to t = 200 (8 344 303 RK4 steps), with
     (Phi, Pi, A, delta, m) stored every 1024 steps and the 64-mode energy
     spectrum of every stored state by the FP64 MFMA projection (8150 spectra,
-    in batches of 512 states).  Progress goes to stderr, one line per chunk."""
+    in batches of 512 states).  Progress goes to stderr, one line per chunk;
+    with `spectra_out` the spectra are saved there (numpy, [states, 64])."""
     import torch
     from paper_1706_07413_amd import inputs as I
     cfg = I.config1()
@@ -207,8 +208,8 @@ def config1_full(adscl, chunk=65536):
     E = E.cpu().numpy()
     con1 = b.constraints()[0]
     st = b.status()
-    if os.path.isdir("gpurun_out"):
-        np.save(os.path.join("gpurun_out", "config1_spectra.npy"), E)
+    if spectra_out:
+        np.save(spectra_out, E)
     tot = E.sum(axis=1)
     return {"workload": "single_twomode_N16385 to t=200, spectra of 64 modes every %d steps" % every,
             "steps": int(st["steps"][0]), "state": int(st["state"][0]), "t": float(st["t"][0]),
@@ -234,7 +235,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient-rate leg")
     ap.add_argument("--adjoint-t", type=float, default=1.0, help="time window of the adjoint leg")
     ap.add_argument("--config1-full", action="store_true",
-                    help="run only the whole 16385-point t=200 run with its spectra (about 11 minutes)")
+                    help="run only the whole 16385-point t=200 run with its spectra (about 7 minutes)")
+    ap.add_argument("--spectra-out", default=None,
+                    help="with --config1-full: save the spectra to this .npy file")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint leg and print its result (for profiling it)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -270,7 +273,7 @@ def main():
         print(json.dumps({"adjoint": adjoint_rate(adscl, args.adjoint_t)}))
         return
     if args.config1_full:
-        print(json.dumps({"config1_full": config1_full(adscl)}))
+        print(json.dumps({"config1_full": config1_full(adscl, spectra_out=args.spectra_out)}))
         return
     T = args.t_end
     eps = torch.tensor(cfg["eps"], dtype=torch.float64, device="cuda")
