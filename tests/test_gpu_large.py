@@ -116,3 +116,24 @@ def test_frozen_metric_on_chunked_grids(Ns, n):
             assert_close(b.split(st[f])[i], ref[f], "frozen N=%d %s" % (N, f))
         assert np.all(b.split(st["A"])[i] == 1.0)
         assert np.all(b.split(st["delta"])[i] == 0.0)
+
+
+@pytest.mark.parametrize("N,frozen,n", [(10001, False, 200), (16385, False, 120), (65537, True, 24)])
+def test_chunks_of_1024_points(monkeypatch, N, frozen, n):
+    """The other chunk shape of the multi-workgroup kernel, (4, 4): 1024 points
+    per workgroup (10001: nine full chunks and 784 points in the last; 65537:
+    64 chunks), selected with ADSCL_TUNE at context creation."""
+    monkeypatch.setenv("ADSCL_TUNE", "%d:4x4" % N)
+    c = np.array([[1.0, 0.6, -0.2]])
+    eps = 0.3 if frozen else 0.05
+    print("chunks of 1024", N, frozen, n, flush=True)
+    b = adscl.Batch([N], n_modes=3, flags=adscl.FROZEN_METRIC if frozen else 0)
+    b.init_modes(np.array([eps]), c)
+    b.step(n, 1e9)
+    st = b.status()
+    assert st["steps"][0] == n
+    g = gpu_state(b)
+    Phi, Pi = O.init_modes(N, eps, c[0])
+    ref = O.evolve(Phi, Pi, n, frozen=frozen)
+    for f in (("Phi", "Pi") if frozen else FIELDS):
+        assert_close(g[f], ref[f], "4x4 chunks N=%d %s" % (N, f))
