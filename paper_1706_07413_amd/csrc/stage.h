@@ -69,9 +69,10 @@ __device__ __forceinline__ double dpp_old(double old, double v)
 // polynomial (truncation below r^6/720 < 4e-17), and the 64 values 2^(j/64)
 // come from a table (t64, in LDS).  Arguments below -746 are raised to -746
 // (e^x is 0 in double there), and so is a NaN (the constraint solve tests q,
-// e^-delta and delta~_{N-1} for finiteness itself); up to x = 2.3e7 the result
-// is e^x within 1.3 ulp, overflowing to +inf through the exponent m, and past
-// that it is not finite.
+// e^-delta and delta~_{N-1} for finiteness itself); up to x = 2.3e7 it is
+// e^x within about 2 ulp (1.3 ulp over [-700, 700] with correctly rounded table
+// entries; the table's own exp2 adds at most its error), overflowing to +inf
+// through the exponent m, and past that it is not finite.
 __device__ __forceinline__ double exp_tab(double x, const double* t64)
 {
     x = __builtin_fmax(x, -746.0);
