@@ -38,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # runs in profiles/evolve_batched1024_hbm.md (scaled by the copy calibration);
 # valid only for the kernel code those counters were taken on (empty while the
 # kernel has changed since).
-MEASURED_TRAFFIC = {(8, 8): 48393824.0}
+MEASURED_TRAFFIC = {(8, 8): 48372288.0}
 
 
 def pt_steps(N, steps):
