@@ -3,9 +3,11 @@
 //
 // One workgroup owns one instance for the whole call and keeps its state on
 // chip: lane l owns the P consecutive grid points l*P .. l*P+P-1 and holds U^n,
-// the RK4 accumulator and the Kreiss-Oliger terms of its points in registers;
-// the stage input and the fluxes are exchanged through lane-interleaved LDS
-// rows.  A stage is
+// the RK4 accumulator and the Kreiss-Oliger terms of its points in registers.
+// On grids that fill every lane (N - 1 = 64 W P) the stage input stays in
+// registers too and neighbours' values cross lanes by DPP, with small LDS
+// slots between wavefronts (no B0 below); otherwise the stage input and the
+// fluxes are exchanged through lane-interleaved LDS rows.  A stage is
 //   B0  stage input (Phi_s, Pi_s) with parity ghosts in LDS; every lane reads
 //       its +-3 window: Kreiss-Oliger terms and q = Phi^2 + Pi^2.
 //   B1  delta~ = -int sin x cos x q  (Eq. (6)) as one prefix sum of
