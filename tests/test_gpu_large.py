@@ -137,3 +137,21 @@ def test_chunks_of_1024_points(monkeypatch, N, frozen, n):
     ref = O.evolve(Phi, Pi, n, frozen=frozen)
     for f in (("Phi", "Pi") if frozen else FIELDS):
         assert_close(g[f], ref[f], "4x4 chunks N=%d %s" % (N, f))
+
+
+def test_dynamic_metric_on_the_speed_table_grid():
+    """The dynamic-metric workload of the paper's speed table, N = 32769 (16
+    chunks of 2048 points), two-mode data 0.05 (e_0 + 0.6 e_1): 40 steps."""
+    N, n = 32769, 40
+    c = np.array([[1.0, 0.6]])
+    print("speed-table grid", N, n, flush=True)
+    b = adscl.Batch([N], a_collapse=0.01, n_modes=2)
+    b.init_modes(np.array([0.05]), c)
+    b.step(n, 1e9)
+    st = b.status()
+    assert st["steps"][0] == n and st["state"][0] == adscl.RUNNING
+    g = gpu_state(b)
+    Phi, Pi = O.init_modes(N, 0.05, c[0])
+    ref = O.evolve(Phi, Pi, n)
+    for f in FIELDS:
+        assert_close(g[f], ref[f], "N=%d %s" % (N, f))
