@@ -139,10 +139,11 @@ def test_chunks_of_1024_points(monkeypatch, N, frozen, n):
         assert_close(g[f], ref[f], "4x4 chunks N=%d %s" % (N, f))
 
 
-def test_dynamic_metric_on_the_speed_table_grid():
-    """The dynamic-metric workload of the paper's speed table, N = 32769 (16
-    chunks of 2048 points), two-mode data 0.05 (e_0 + 0.6 e_1): 40 steps."""
-    N, n = 32769, 40
+@pytest.mark.parametrize("N,n", [(32769, 40), (65537, 24)])
+def test_dynamic_metric_on_the_speed_table_grids(N, n):
+    """The dynamic metric on the paper's speed-table grids: N = 32769 (16
+    chunks of 2048 points) and the largest supported N = 65537 (32 chunks),
+    two-mode data 0.05 (e_0 + 0.6 e_1)."""
     c = np.array([[1.0, 0.6]])
     print("speed-table grid", N, n, flush=True)
     b = adscl.Batch([N], a_collapse=0.01, n_modes=2)
