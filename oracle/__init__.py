@@ -28,6 +28,22 @@ _i64 = ctypes.c_int64
 _p = ctypes.POINTER(ctypes.c_double)
 
 
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_BATCH_SIG = {
+    "ora_threads": (_i, []),
+    "ora_evolve_gaussian_batch": (None, [_i, _i32p, _p, _p, _i, _d, _d, _d, _i64p, _i64p, _i32p]),
+    "ora_objective_batch": (None, [_i, _i32p, _i, _d, _d, _d, _p, _i, _p, _i, _i64p, _i64, _p, _p, _i32p]),
+}
+
+
+def _bind(lib, sig):
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -36,6 +52,7 @@ def _load():
         from . import build as _b  # noqa: F401  (build on first use in a checkout)
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
+    _bind(lib, _BATCH_SIG)
     sig = {
         "ora_tables": (None, [_i, _p, _p, _p, _p, _p]),
         "ora_op_D": (None, [_i, _d, _p, _i, _i, _p]),
@@ -47,6 +64,7 @@ def _load():
                             _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
         "ora_mass_paper": (_d, [_i, _p, _p, _p]),
         "ora_residuals": (None, [_i, _p, _p, _p, _p, _p, _p]),
+        "ora_adot_residual": (None, [_i, _i, _d, _p, _p, _p, _p]),
         "ora_jacobi": (_d, [_i, _d, _d, _d]),
         "ora_modes": (None, [_i, _i, _p, _p]),
         "ora_spectrum": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
@@ -182,6 +200,18 @@ def residuals(Phi, Pi, A, delta):
     return RA, Rd
 
 
+def adot_residual(Phi, Pi, gauge=GAUGE_BOUNDARY, ko=0.5):
+    """Eq. (4) residual of one state: the metric is solved from (Phi, Pi), A_t is
+    the derivative of that solve along the right-hand sides (Phi_t, Pi_t).
+    Returns (Adot, R), R = A_t + 2 sin x cos x A^2 e^-delta Phi Pi (0 at the ends)."""
+    lib = _load()
+    Phi, Pi = _f64(Phi), _f64(Pi)
+    N = len(Phi)
+    Ad, R = np.empty(N), np.empty(N)
+    lib.ora_adot_residual(N, gauge, ko, _ptr(Phi), _ptr(Pi), _ptr(Ad), _ptr(R))
+    return Ad, R
+
+
 def jacobi(n, a, b, z):
     return _load().ora_jacobi(n, a, b, z)
 
@@ -215,6 +245,55 @@ def init_modes(N, eps, c):
     Phi, Pi = np.empty(N), np.empty(N)
     lib.ora_init_modes(N, eps, len(c), _ptr(c), _ptr(Phi), _ptr(Pi))
     return Phi, Pi
+
+
+# ---------------------------------------------------------------------------
+# Batches: independent instances over the host's cores (adscl_oracle_batch.c)
+# ---------------------------------------------------------------------------
+
+def timing_lib(path):
+    """The -O3 -march=native timing build at `path` (see build.build_timing),
+    with the batch drivers bound; pass it as ``lib=`` to the batch functions."""
+    lib = ctypes.CDLL(path)
+    _bind(lib, _BATCH_SIG)
+    return lib
+
+
+def threads(lib=None):
+    """OpenMP threads the batch drivers of `lib` (default: the parity build) use."""
+    return (lib or _load()).ora_threads()
+
+
+def evolve_gaussian_batch(Ns, eps, sigma, n_stop, gauge=GAUGE_BOUNDARY, cfl=0.25, ko=0.5, a_collapse=0.0,
+                          lib=None):
+    """Gaussian data for every instance evolved to n_stop[b] steps or collapse,
+    one instance per thread; returns (steps, state) arrays."""
+    L = lib or _load()
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    n = len(Ns)
+    eps, sigma = _f64(eps), _f64(sigma)
+    ns = np.ascontiguousarray(np.broadcast_to(np.asarray(n_stop, np.int64), (n,)))
+    steps = np.zeros(n, np.int64)
+    state = np.zeros(n, np.int32)
+    L.ora_evolve_gaussian_batch(n, Ns.ctypes.data_as(_i32p), _ptr(eps), _ptr(sigma), gauge, cfl, ko, a_collapse,
+                                ns.ctypes.data_as(_i64p), steps.ctypes.data_as(_i64p), state.ctypes.data_as(_i32p))
+    return steps, state
+
+
+def objective_batch(Ns, eps, c, J, n_steps, K, gauge=GAUGE_BOUNDARY, cfl=0.25, ko=0.5, a_collapse=0.0, lib=None):
+    """``objective`` for every instance, one instance per thread; returns
+    (L [n], grad [n, Jc], valid [n])."""
+    L_ = lib or _load()
+    Ns = np.ascontiguousarray(Ns, dtype=np.int32)
+    n = len(Ns)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    eps = _f64(eps)
+    ns = np.ascontiguousarray(np.broadcast_to(np.asarray(n_steps, np.int64), (n,)))
+    Lv, g = np.zeros(n), np.zeros((n, c.shape[1]))
+    valid = np.zeros(n, np.int32)
+    L_.ora_objective_batch(n, Ns.ctypes.data_as(_i32p), gauge, cfl, ko, a_collapse, _ptr(eps), c.shape[1], _ptr(c),
+                           int(J), ns.ctypes.data_as(_i64p), int(K), _ptr(Lv), _ptr(g), valid.ctypes.data_as(_i32p))
+    return Lv, g, valid
 
 
 # ---------------------------------------------------------------------------

@@ -439,6 +439,74 @@ void ora_residuals(int N, const double* Phi, const double* Pi, const double* A, 
     grid_free(&g);
 }
 
+/*
+ * Residual of Eq. (4), A_t = -2 sin x cos x A^2 e^-delta Phi Pi, which the scheme
+ * never imposes (Sec. II monitors the residuals of the equations).  A_t is the
+ * time derivative of the discrete A of constraint_solve along the semi-discrete
+ * flow, i.e. the derivative of A(Phi, Pi) in the direction of the right-hand
+ * sides (Phi_t, Pi_t) of rhs_eval, taken through every step of the solve:
+ *   q_t = 2 (Phi Phi_t + Pi Pi_t),   p_t = sin x cos x q_t (0 at both ends),
+ *   delta~_t: 0 at x = 0, delta~_t,{i+1} = delta~_t,i - cell4(p_t)_i,
+ *   E = e^{-delta~}:  E_t = -E delta~_t,
+ *   sigma_t = tan^2 x (q_t E + q E_t) (0 at both ends),
+ *   S_t: 0 at x = 0, S_t,{i+1} = S_t,i + cell4(sigma_t)_i,
+ *   m = S / E:  m_t = (S_t - m E_t) / E,
+ *   A = 1 - cos^3 x / sin x m:  A_t = -cos^3 x / sin x m_t  (0 at both ends).
+ * Outputs, N values each: Adot = A_t and R = A_t + 2 sin x cos x A^2 e^-delta Phi Pi
+ * (both 0 at the end points, where A is pinned).  The metric is the solve's of
+ * (Phi, Pi) in the given gauge; ko is the Kreiss-Oliger coefficient of the
+ * right-hand sides.
+ */
+void ora_adot_residual(int N, int gauge, double ko, const double* Phi, const double* Pi,
+                       double* Adot, double* R)
+{
+    ora_grid g;
+    ora_cwork w;
+    ora_rwork r;
+    double *A, *delta, *m, *dPhi, *dPi, *qt, *pt, *dt, *Et, *st, *St;
+    double h;
+    int i;
+    grid_make(&g, N);
+    cwork_alloc(&w, N);
+    rwork_alloc(&r, N);
+    h = g.h;
+    A = malloc(sizeof(double) * N); delta = malloc(sizeof(double) * N); m = malloc(sizeof(double) * N);
+    dPhi = malloc(sizeof(double) * N); dPi = malloc(sizeof(double) * N);
+    qt = malloc(sizeof(double) * N); pt = malloc(sizeof(double) * N); dt = malloc(sizeof(double) * N);
+    Et = malloc(sizeof(double) * N); st = malloc(sizeof(double) * N); St = malloc(sizeof(double) * N);
+
+    constraint_solve(&g, gauge, Phi, Pi, &w, A, delta, m);
+    rhs_eval(&g, ko, 0, Phi, Pi, A, delta, &r, dPhi, dPi);
+
+    for (i = 0; i < N; ++i) qt[i] = 2.0 * (Phi[i] * dPhi[i] + Pi[i] * dPi[i]);
+    for (i = 0; i < N; ++i) pt[i] = g.sc[i] * qt[i];
+    pt[0] = 0.0;
+    pt[N - 1] = 0.0;
+    dt[0] = 0.0;
+    for (i = 0; i < N - 1; ++i) dt[i + 1] = dt[i] - cell4(pt, N, i, h, -1.0, -1.0);
+    for (i = 0; i < N; ++i) Et[i] = -w.E[i] * dt[i];
+    for (i = 0; i < N; ++i) st[i] = g.t2[i] * (qt[i] * w.E[i] + w.q[i] * Et[i]);
+    st[0] = 0.0;
+    st[N - 1] = 0.0;
+    St[0] = 0.0;
+    for (i = 0; i < N - 1; ++i) St[i + 1] = St[i] + cell4(st, N, i, h, 1.0, 1.0);
+    for (i = 0; i < N; ++i) {
+        if (i == 0 || i == N - 1) {
+            Adot[i] = 0.0;
+            R[i] = 0.0;
+            continue;
+        }
+        Adot[i] = -g.c3s[i] * ((St[i] - m[i] * Et[i]) / w.E[i]);
+        R[i] = Adot[i] + 2.0 * g.sc[i] * A[i] * A[i] * exp(-delta[i]) * Phi[i] * Pi[i];
+    }
+
+    free(A); free(delta); free(m); free(dPhi); free(dPi);
+    free(qt); free(pt); free(dt); free(Et); free(st); free(St);
+    rwork_free(&r);
+    cwork_free(&w);
+    grid_free(&g);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Linear AdS4 eigenmodes (Sec. II: normal-mode spectrum)                    */
 /* ------------------------------------------------------------------------ */

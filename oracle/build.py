@@ -1,29 +1,46 @@
-"""Build the CPU FP64 oracle shared library (test infrastructure only).
+"""Build the CPU FP64 oracle shared libraries (test infrastructure only).
 
-The oracle is compiled with ``-O2 -ffp-contract=off -fno-fast-math`` so that
-every floating-point expression is evaluated exactly as written (no FMA
-contraction, no reassociation).  Run ``python oracle/build.py``; the package's
-build entry point calls :func:`build` as well.
+liboracle.so, the parity build, is compiled with ``-O2 -ffp-contract=off
+-fno-fast-math`` so that every floating-point expression is evaluated exactly
+as written (no FMA contraction, no reassociation).  The timing build of the CPU
+baseline (:func:`build_timing`) is the same sources at ``-O3 -march=native``
+(still no contraction and no fast-math, so it computes the same numbers); it is
+compiled on the machine that runs it, since ``-march=native`` code need not run
+on another host.  Both link OpenMP, which only the batch drivers use (one
+instance per thread).  Run ``python oracle/build.py``; the package's build
+entry point calls :func:`build` as well.
 """
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["adscl_oracle.c", "adscl_oracle_adj.c"]
+SOURCES = ["adscl_oracle.c", "adscl_oracle_adj.c", "adscl_oracle_batch.c"]
 LIB = os.path.join(HERE, "liboracle.so")
-FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
-         "-Wall", "-Wextra", "-Wno-unused-parameter"]
+COMMON = ["-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+          "-Wall", "-Wextra", "-Wno-unused-parameter"]
+PARITY_FLAGS = ["-O2"] + COMMON
+TIMING_FLAGS = ["-O3", "-march=native"] + COMMON
 
 
-def build(verbose=False):
-    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["gcc"] + FLAGS + srcs + ["-o", LIB + ".tmp", "-lm"]
+def _gcc(flags, out, verbose):
+    cmd = ["gcc"] + flags + [os.path.join(HERE, s) for s in SOURCES] + ["-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def build(verbose=False):
+    """The parity build, in-tree."""
+    return _gcc(PARITY_FLAGS, LIB, verbose)
+
+
+def build_timing(out, verbose=False):
+    """The -O3 -march=native timing build, written to `out` (a path outside the
+    tree, made on the host that will run it)."""
+    return _gcc(TIMING_FLAGS, out, verbose)
 
 
 if __name__ == "__main__":

@@ -368,6 +368,72 @@ def test_adot_residual_order4():
     assert rate(out[0], out[1]) > 3.3 and rate(out[1], out[2]) > 3.5, out
 
 
+def _gauss_at(N, T=0.5, eps=3.0, sigma=0.25, gauge=O.GAUGE_BOUNDARY):
+    Phi, Pi = O.init_gaussian(N, eps, sigma)
+    return O.evolve(Phi, Pi, O.n_steps_for(T, N), gauge=gauge)
+
+
+def test_adot_residual_function_order4():
+    """The library's Eq. (4) diagnostic as the oracle defines it (A_t the
+    derivative of the constraint solve along the right-hand sides): its
+    residual converges to zero at order 4 on a nonlinear Gaussian."""
+    out = []
+    for N in (129, 257, 513, 1025):
+        r = _gauss_at(N)
+        _, R = O.adot_residual(r["Phi"], r["Pi"])
+        assert R[0] == 0.0 and R[-1] == 0.0
+        out.append(np.max(np.abs(R)))
+    for e1, e2 in zip(out, out[1:]):
+        assert 3.7 < rate(e1, e2) < 4.3, out
+
+
+def test_adot_is_the_derivative_of_the_constraint_solve():
+    """A_t against central differences of the oracle's constraint solve along
+    the direction (Phi_t, Pi_t): A(U + tau F) - A(U - tau F) over 2 tau, in both
+    gauges (A does not depend on the gauge, the right-hand sides do)."""
+    N = 257
+    for gauge in (O.GAUGE_BOUNDARY, O.GAUGE_ORIGIN):
+        r = _gauss_at(N, gauge=gauge)
+        Phi, Pi = r["Phi"], r["Pi"]
+        c = O.constraints(Phi, Pi, gauge)
+        dPhi, dPi = O.rhs(Phi, Pi, c["A"], c["delta"])
+        Ad, _ = O.adot_residual(Phi, Pi, gauge=gauge)
+        tau = 1e-5
+        Ap = O.constraints(Phi + tau * dPhi, Pi + tau * dPi, gauge)["A"]
+        Am = O.constraints(Phi - tau * dPhi, Pi - tau * dPi, gauge)["A"]
+        fd = (Ap - Am) / (2 * tau)
+        assert np.max(np.abs(Ad - fd)) <= 1e-8 * np.max(np.abs(Ad)), gauge
+
+
+def test_adot_matches_time_difference_of_the_evolution():
+    """A_t of the diagnostic against the 5-level 4th-order time difference of A
+    over RK4 steps around the same state: they differ by the O(dt^4) error of
+    the difference and of the time integrator only."""
+    diffs = []
+    for N in (257, 513):
+        Phi, Pi = O.init_gaussian(N, 3.0, 0.25)
+        n_mid = O.n_steps_for(0.5, N)
+        r = O.evolve(Phi, Pi, n_mid + 2, snap_every=1, n_slots=n_mid + 3)
+        S = r["snaps"]
+        dt = O.dt_of(N)
+        Atd = (S[n_mid - 2, 2] - 8 * S[n_mid - 1, 2] + 8 * S[n_mid + 1, 2] - S[n_mid + 2, 2]) / (12 * dt)
+        Ad, _ = O.adot_residual(S[n_mid, 0], S[n_mid, 1])
+        diffs.append(np.max(np.abs(Ad - Atd)[1:-1]) / np.max(np.abs(Ad)))
+    assert diffs[0] < 1e-6 and rate(diffs[0], diffs[1]) > 3.5, diffs
+
+
+def test_adot_vanishes_for_time_symmetric_data_without_dissipation():
+    """Phi = 0 and no Kreiss-Oliger term: Pi_t = cot^2 x D(tan^2 x A e^-delta Phi) = 0
+    and the origin row 3 D(A e^-delta Phi) = 0, so q_t = 0 and A_t = 0 exactly;
+    Eq. (4) gives 0 as well (Phi Pi = 0)."""
+    for N in (65, 257):
+        Phi, Pi = O.init_gaussian(N, 5.0, 0.2)
+        Ad, R = O.adot_residual(Phi, Pi, ko=0.0)
+        assert np.all(Ad == 0.0) and np.all(R == 0.0)
+        Ad, R = O.adot_residual(Phi, Pi, ko=0.5)  # the dissipation alone: O(h^5) rounding-free
+        assert 0.0 < np.max(np.abs(Ad)) < 1e-4
+
+
 def test_boundary_conditions_hold_at_every_snapshot():
     N = 257
     for gauge in (O.GAUGE_BOUNDARY, O.GAUGE_ORIGIN):
