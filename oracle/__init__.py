@@ -62,6 +62,8 @@ def _load():
         "ora_rhs": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p]),
         "ora_evolve": (_i, [_i, _i, _i, _d, _d, _d, _p, _p, _i64, _i64, ctypes.c_int32, _i64, _p,
                             _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
+        "ora_evolve_scheme": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _p, _p, _p, _i64, _i64, ctypes.c_int32, _i64,
+                                   _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
         "ora_mass_paper": (_d, [_i, _p, _p, _p]),
         "ora_residuals": (None, [_i, _p, _p, _p, _p, _p, _p]),
         "ora_adot_residual": (None, [_i, _i, _d, _p, _p, _p, _p]),
@@ -183,6 +185,34 @@ def evolve(Phi, Pi, n_stop, n0=0, gauge=GAUGE_BOUNDARY, frozen=False, cfl=0.25, 
     return dict(Phi=Phi, Pi=Pi, A=A, delta=delta, m=m, steps=n_out.value, state=st,
                 minA=minA.value, t=n_out.value * dt, t_c=tc.value,
                 snaps=snaps[:n_slots] if n_slots > 0 else None)
+
+
+def evolve_scheme(Phi, Pi, n_stop, rk=4, a_reint=0, A=None, n0=0, gauge=GAUGE_BOUNDARY, frozen=False, cfl=0.25,
+                  ko=0.5, a_collapse=0.0, snap_every=0, n_slots=0, n_final=None):
+    """``evolve`` with the scheme options of Sec. II: Runge-Kutta order ``rk``
+    (2 and 3: the Shu-Osher SSP methods; 4: classical) and ``a_reint`` (0: A
+    from Eq. (5) at every stage; K >= 1: A evolved with Eq. (4) and replaced
+    by Eq. (5)'s at every step that is a multiple of K).  ``A``: the state's
+    evolved A at n0 (needed only when A is evolved and n0 is not a multiple of
+    K).  Returns the dict of ``evolve`` (A the state's A)."""
+    lib = _load()
+    Phi, Pi = _f64(Phi).copy(), _f64(Pi).copy()
+    N = len(Phi)
+    A = np.ones(N) if A is None else _f64(A).copy()
+    delta, m = np.empty(N), np.empty(N)
+    snaps = np.zeros((max(n_slots, 1), 5, N))
+    n_out = _i64(0)
+    minA, tc = _d(0), _d(0)
+    st = lib.ora_evolve_scheme(N, gauge, int(frozen), cfl, ko, a_collapse, int(rk), int(a_reint), _ptr(Phi), _ptr(Pi),
+                               _ptr(A), n0, n_stop, snap_every, n_slots, _ptr(snaps), _ptr(delta), _ptr(m),
+                               ctypes.byref(n_out), ctypes.byref(minA), ctypes.byref(tc))
+    if st < 0:
+        raise ValueError("invalid scheme option")
+    n_final = n_stop if n_final is None else n_final
+    if st == RUNNING and n_out.value >= n_final:
+        st = DONE
+    return dict(Phi=Phi, Pi=Pi, A=A, delta=delta, m=m, steps=n_out.value, state=st, minA=minA.value,
+                t=n_out.value * dt_of(N, cfl), t_c=tc.value, snaps=snaps[:n_slots] if n_slots > 0 else None)
 
 
 def mass_paper(Phi, Pi, A):

@@ -15,7 +15,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["adscl_oracle.c", "adscl_oracle_adj.c", "adscl_oracle_batch.c"]
+SOURCES = ["adscl_oracle.c", "adscl_oracle_adj.c", "adscl_oracle_batch.c", "adscl_oracle_scheme.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 COMMON = ["-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
