@@ -27,18 +27,49 @@ import numpy as np  # noqa: E402
 
 METRIC = "FP64 grid-point RK4 updates/s, batched vs single-instance; adjoint grads/s"
 UNIT = "grid-point RK4 updates/s"
-# Algorithmic work per grid point per RK4 stage of the scheme:
-# 76 FP64 add/mul/fma-terms of the constraint scans, fluxes, D and KO stencils
-# and RK combination, plus one exp counted at 24 flops.
-FLOP_PER_PT_STAGE = 100.0
+# Algorithmic work per grid point per RK4 stage of the scheme, counted from its
+# definition (exp and the reciprocal are not counted as flops): q 3; p and sigma
+# pre-multiplies 2; two 4-point cell rules 12; two scan adds 2; sigma E 1;
+# m, A, e^-delta 4; w, f1, f2, g 4; two D stencils and cot^2 x 11; two KO
+# stencils 18; right-hand-side adds 2; RK4 combination 8.
+FLOP_PER_PT_STAGE = 67.0
 BYTES_PER_PT_STEP = 32.0          # read (Phi, Pi)^n, write (Phi, Pi)^{n+1}
-PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector peak
+PEAK_FP64_TFLOPS = 78.6           # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
+VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9   # FP64 vector issue ceiling, lane-instructions/s
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE
-# runs in profiles/evolve_batched1024_hbm.md (scaled by the copy calibration);
-# valid only for the kernel code those counters were taken on (empty while the
-# kernel has changed since).
-MEASURED_TRAFFIC = {(8, 8): 48372288.0}
+# Counter figures of the dominant kernel (HBM bytes per launch from FETCH_SIZE /
+# WRITE_SIZE scaled by the copy calibration; VALU and FP64 instructions per
+# pt-stage from the SQ counters) are read from the profile summary, and only
+# when the digest of the forward kernel's sources it records is the digest of
+# the sources in this tree: after any change to the kernel they are null until
+# measured again.
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "evolve_batched1024_counters.md")
+KERNEL_SOURCES = ["paper_1706_07413_amd/csrc/stage.h", "paper_1706_07413_amd/csrc/evolve.hip",
+                  "paper_1706_07413_amd/csrc/internal.h", "paper_1706_07413_amd/build.py"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_figures():
+    """{"P": .., "W": .., "traffic_bytes": .., "valu_per_pt_stage": .., "fp64_flop_per_pt_stage": ..}
+    of the profile summary if it was measured on this tree's kernel, else None."""
+    try:
+        with open(COUNTER_PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    dig = [l.split(":", 1)[1].strip() for l in lines if l.startswith("kernel-source-digest:")]
+    fig = [l.split(":", 1)[1].strip() for l in lines if l.startswith("bench-figures:")]
+    if not dig or not fig or dig[0] != kernel_digest():
+        return None
+    return json.loads(fig[0])
 
 
 def pt_steps(N, steps):
@@ -63,6 +94,7 @@ def adjoint_rate(adscl, T, iters=2):
     _, hist, active = b.descend(eps, c, cfg["J_obj"], T, iters, ckpt_every=cfg["ckpt_every"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    b.close()
     n = len(cfg["N"])
     steps = np.ceil(T / (0.25 * (math.pi / 2) / (np.asarray(cfg["N"], np.float64) - 1)) - 1e-9)
     return {"workload": "batched_adjoint_gd_256: 256 instances, N in {2049,4097}, eps log-U[0.02,0.2], 32 modes, "
@@ -72,25 +104,43 @@ def adjoint_rate(adscl, T, iters=2):
             "active": int(active.sum().item())}
 
 
-def cpu_baseline(cfg, seconds):
-    """The oracle, single-threaded, on the first instances of the workload for a
-    fixed number of steps each, until about `seconds` of CPU work is done."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, n_inst=64, steps=4096):
+    """The oracle on the host's cores: the first `n_inst` instances of the
+    workload, `steps` RK4 steps each (or to collapse), one instance per OpenMP
+    thread, in the parity build (gcc -O2 -ffp-contract=off) and in a timing build
+    of the same sources (-O3 -march=native, compiled here for this host)."""
+    import tempfile
+
     import oracle as O
-    work, t_used, n_inst = 0.0, 0.0, 0
-    steps = 256
-    t0 = time.perf_counter()
-    for i in range(len(cfg["N"])):
-        N = int(cfg["N"][i])
-        Phi, Pi = O.init_gaussian(N, float(cfg["eps"][i]), float(cfg["sigma"][i]))
-        r = O.evolve(Phi, Pi, steps, gauge=cfg["gauge"], a_collapse=cfg["a_collapse"])
-        work += N * r["steps"]
-        n_inst += 1
-        t_used = time.perf_counter() - t0
-        if t_used >= seconds:
-            break
-    return dict(value=work / t_used, unit=UNIT, cores=1, kind="oracle",
-                sample="first %d instances of the 1024-instance workload, %d RK4 steps each, "
-                       "oracle (gcc -O2, 1 thread)" % (n_inst, steps))
+    from oracle import build as OB
+    Ns, eps, sig = cfg["N"][:n_inst], cfg["eps"][:n_inst], cfg["sigma"][:n_inst]
+    out = {}
+    timing_so = os.path.join(tempfile.mkdtemp(prefix="adscl_oracle_"), "liboracle_timing.so")
+    OB.build_timing(timing_so)
+    for name, lib in (("O2", None), ("O3_native", O.timing_lib(timing_so))):
+        t0 = time.perf_counter()
+        st, _ = O.evolve_gaussian_batch(Ns, eps, sig, steps, gauge=cfg["gauge"], a_collapse=cfg["a_collapse"],
+                                        lib=lib)
+        dt = time.perf_counter() - t0
+        out[name] = (pt_steps(Ns, st) / dt, O.threads(lib))
+    v, cores = out["O3_native"]
+    return dict(value=v, unit=UNIT, cores=cores, kind="oracle",
+                sample="first %d instances of the 1024-instance workload (N in {1025,2049,4097}), %d RK4 steps "
+                       "each or to collapse, one instance per OpenMP thread; oracle sources built -O3 "
+                       "-march=native -ffp-contract=off (timing build)" % (n_inst, steps),
+                parity_build_value=out["O2"][0], parity_build="gcc -O2 -ffp-contract=off",
+                nproc=os.cpu_count(), cpu_model=cpu_model())
 
 
 # kernel configurations at the tightest lane capacity of each benchmark grid
@@ -140,6 +190,7 @@ def large_instance_rate(adscl, steps=4096):
     b.step(steps, 1e9)
     b.sync()
     dt = time.perf_counter() - t0
+    b.close()
     N = int(cfg["N"][0])
     return {"workload": "single_twomode_N16385 (t=200 run), a window of %d RK4 steps" % steps,
             "pt_steps_per_s": N * steps / dt, "us_per_step": dt / steps * 1e6,
@@ -208,6 +259,7 @@ def config1_full(adscl, chunk=65536, spectra_out=None):
     E = E.cpu().numpy()
     con1 = b.constraints()[0]
     st = b.status()
+    b.close()
     if spectra_out:
         np.save(spectra_out, E)
     tot = E.sum(axis=1)
@@ -229,7 +281,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--t-end", type=float, default=50.0,
                     help="end time of every pass (default: the workload's full run, 50)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-instances", type=int, default=64,
+                    help="instances of the CPU baseline's sample (the workload's first ones)")
+    ap.add_argument("--cpu-steps", type=int, default=4096, help="RK4 steps per instance of that sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient-rate leg")
@@ -305,7 +359,11 @@ def main():
     k = int(np.argmax(work_k))
     unit_steps = work_k[k]
     ms = classes[k]["last_ms"]
-    achieved = unit_steps * 4 * FLOP_PER_PT_STAGE / (ms * 1e-3) / 1e12
+    pt_stage_rate = unit_steps * 4 / (ms * 1e-3)
+    achieved = pt_stage_rate * FLOP_PER_PT_STAGE / 1e12
+    cf = counter_figures()
+    if cf is not None and (cf.get("P"), cf.get("W")) != (classes[k]["P"], classes[k]["W"]):
+        cf = None
     states = np.bincount(st["state"], minlength=4)
     per_n = {}
     for n in (1025, 2049, 4097):
@@ -333,10 +391,19 @@ def main():
                    "collapsed": int(states[1]), "done": int(states[3]), "by_N": per_n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": MEASURED_TRAFFIC.get((classes[k]["P"], classes[k]["W"])),
+                     "traffic": cf["traffic_bytes"] if cf else None,
                      "kernel": "evolve_kernel<P=%d,W=%d> (%d instances)" % (classes[k]["P"], classes[k]["W"],
                                                                           classes[k]["members"]),
-                     "launch_ms": ms, "flop_per_pt_stage": FLOP_PER_PT_STAGE},
+                     "launch_ms": ms, "pt_stages_per_launch": unit_steps * 4,
+                     "flop_per_pt_stage": FLOP_PER_PT_STAGE, "flop_count": "algorithmic, from the scheme",
+                     "kernel_source_digest": kernel_digest(),
+                     # from the SQ counters of this kernel (null when the kernel changed since)
+                     "executed_fp64_flop_per_pt_stage": cf["fp64_flop_per_pt_stage"] if cf else None,
+                     "executed_frac": (pt_stage_rate * cf["fp64_flop_per_pt_stage"] / 1e12 / PEAK_FP64_TFLOPS
+                                       if cf else None),
+                     "valu_instr_per_pt_stage": cf["valu_per_pt_stage"] if cf else None,
+                     "valu_issue_frac": (pt_stage_rate * cf["valu_per_pt_stage"] / VALU_LANE_INSTR_PER_S
+                                         if cf else None)},
         "effective_hbm_GBs": value * BYTES_PER_PT_STEP / 1e9,
         "launches": classes,
         "autotune": {str(N): {"P": P, "W": W, "pt_steps_per_s": r} for N, (P, W, r) in tuned.items()},
@@ -355,8 +422,10 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_rate(adscl, args.adjoint_t)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_instances, args.cpu_steps)
+    batch.close()
+    torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

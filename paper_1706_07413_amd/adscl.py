@@ -5,8 +5,10 @@ of the library.  Device arrays are torch tensors on the context's GPU (their
 data pointers go straight through the ABI); host arrays are numpy arrays.  The
 module refuses to work without the built library.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -124,8 +126,29 @@ def _ptr_mem(a):
     if isinstance(a, torch.Tensor):
         if a.dtype != torch.float64 or not a.is_contiguous():
             raise TypeError("tensors must be contiguous float64")
-        return a.data_ptr(), (MEM_DEVICE if a.is_cuda else MEM_HOST)
+        if a.is_cuda:
+            # the context's stream is not ordered after torch's streams: work
+            # torch has queued that writes this tensor must be done before the
+            # library reads it
+            torch.cuda.current_stream(a.device).synchronize()
+            return a.data_ptr(), MEM_DEVICE
+        return a.data_ptr(), MEM_HOST
     raise TypeError("expected numpy array or torch tensor")
+
+
+# Contexts still open at interpreter exit are destroyed by an exit handler,
+# while the HIP runtime is still intact, rather than by __del__ during the
+# interpreter's final teardown (when the runtime's own state may be gone).
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for b in list(_live):
+        try:
+            b.close()
+        except Exception:
+            pass
 
 
 class Batch:
@@ -145,6 +168,7 @@ class Batch:
         if rc != OK:
             raise AdsclError(rc, L.adscl_last_error(None).decode())
         self._h = h
+        _live.add(self)
         self.n_inst = len(self._N)
         self.cfl = cfl
         off = np.zeros(self.n_inst, np.int64)
@@ -159,9 +183,18 @@ class Batch:
             raise AdsclError(rc, lib().adscl_last_error(self._h).decode())
 
     def close(self):
+        """Synchronise the context's stream and free everything it holds."""
         if getattr(self, "_h", None):
+            lib().adscl_sync(self._h)
             lib().adscl_destroy(self._h)
             self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

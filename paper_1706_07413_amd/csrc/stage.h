@@ -191,7 +191,7 @@ struct Stage {
     static constexpr bool LT = FWD && EDGE;
     static constexpr bool ROWS = !EDGE;
     static constexpr size_t lds_doubles = (ROWS ? (size_t)4 * SLOTS + 2 * NL : 0)
-                                          + (EDGE ? (size_t)36 * (W + 2) + 20 * W : 0) + (LT ? (size_t)3 * P * NL : 0)
+                                          + (EDGE ? (size_t)44 * (W + 2) + 20 * W : 0) + (LT ? (size_t)3 * P * NL : 0)
                                           + 4 * W + 8 + 64;
 
     double2* U;     // (Phi_s, Pi_s) rows
@@ -205,7 +205,10 @@ struct Stage {
     double2* XU;    // [2 buffers][W+2][6] points 0..2 of lane 0, then P-1..P-3 of lane 63
     double* XP;     // [W+2][2] p of the first point of lane 0, of the last point of lane 63
     double* XS;     // [W+2][2] the same for sigma
-    double2* XF;    // [W+2][4] fluxes of points 0, 1 of lane 0 and P-1, P-2 of lane 63
+    double2* XF;    // [2 buffers][W+2][4] fluxes of points 0, 1 of lane 0 and P-1, P-2 of lane 63;
+                    // the buffer follows XU's, since with the metric frozen B3 is the only
+                    // barrier of a stage and a wavefront may write its next stage's fluxes
+                    // while its neighbour still reads this stage's
     double2* RU;    // EDGE, adjoint: [W][6] row cotangents (Phi_t, Pi_t) of points 0..2 of lane 0, P-1..P-3 of lane 63
     double* RF;     // EDGE, adjoint: [W][4] cotangents of the D g rows, points 0, 1 of lane 0, P-1, P-2 of lane 63
     double* RSb;    // EDGE, adjoint: [W][2] S-bar of the first point of lane 0, of the last point of lane 63
@@ -245,7 +248,7 @@ struct Stage {
             XS = p;
             p += 2 * (W + 2);
             XF = reinterpret_cast<double2*>(p);
-            p += 8 * (W + 2);
+            p += 16 * (W + 2);
             RU = reinterpret_cast<double2*>(p);
             p += 12 * W;
             RF = p;
@@ -650,9 +653,12 @@ struct Stage {
     }
 
     // rhs on the edge path.  No barrier before the scans: the stage input is in
-    // registers and its edges were published before the first scan barrier;
-    // both edge buffers' last readers are separated from their next writers by
-    // at least one barrier of the next stage.
+    // registers and its edges were published before the first scan barrier.
+    // The stage-input and flux slots (XU, XF) are double-buffered by stage, so
+    // their last readers (after B3) never meet the next stage's writers even
+    // with the metric frozen, when B3 is a stage's only barrier; the scan slots
+    // (XP, XS) are written before B1 / B2 and read after them, with B3 between
+    // a stage's reads and the next stage's writes.
     template <bool KEEP>
     __device__ __forceinline__ int rhs_edge(bool check, bool frozen, const double* v0, const double* v1, double* r0,
                                             double* r1, ADSCL_GLOBAL double* ES, int fE)
@@ -695,8 +701,9 @@ struct Stage {
                 chk = fma(E[k], 0.0, chk);
             }
         }
+        double2* const XFb = XF + buf * (W + 2) * 4;  // this stage's flux slots
         {
-            double2* xf = XF + (wv + 1) * 4;
+            double2* xf = XFb + (wv + 1) * 4;
             if (lane == 0) {
                 xf[0] = make_double2(ff[0], fg[0]);
                 xf[1] = make_double2(ff[1], fg[1]);
@@ -706,13 +713,13 @@ struct Stage {
                 xf[3] = make_double2(ff[P - 2], fg[P - 2]);
             }
             if (tid == 0) {  // f1 even, g odd about x = 0: points -1, -2
-                XF[2] = make_double2(ff[1], -fg[1]);
-                XF[3] = make_double2(ff[2], -fg[2]);
+                XFb[2] = make_double2(ff[1], -fg[1]);
+                XFb[3] = make_double2(ff[2], -fg[2]);
             }
             if (tid == NL - 1) {
                 // f1_{N-1} = 0, g_{N-1} the even 6th-order extrapolation; ghost N
-                XF[(W + 1) * 4] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
-                XF[(W + 1) * 4 + 1] = make_double2(-ff[P - 1], fg[P - 1]);
+                XFb[(W + 1) * 4] = make_double2(0.0, (15.0 * fg[P - 1] - 6.0 * fg[P - 2] + fg[P - 3]) / 10.0);
+                XFb[(W + 1) * 4 + 1] = make_double2(-ff[P - 1], fg[P - 1]);
             }
         }
         if (check) {
@@ -755,8 +762,8 @@ struct Stage {
         }
         double2 fw[P + 4];  // points i0-2 .. i0+P+1
         {
-            const double2* xl = XF + wv * 4;
-            const double2* xr = XF + (wv + 2) * 4;
+            const double2* xl = XFb + wv * 4;
+            const double2* xr = XFb + (wv + 2) * 4;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const double2 gl = xl[3 - r], gr = xr[r];

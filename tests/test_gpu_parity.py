@@ -125,6 +125,32 @@ def test_frozen_metric():
         assert np.all(b.split(st["A"])[i] == 1.0)
 
 
+# full-lane configurations (N - 1 = 64 W P) with more than one wavefront: with
+# the metric frozen the flux barrier is a stage's only barrier, so these are the
+# cases where wavefronts exchange edge values across stages without a scan
+# barrier between them
+FULL_MULTIWAVE = [(513, 4, 2), (1025, 4, 4), (1025, 8, 2), (2049, 4, 8), (2049, 8, 4), (2049, 16, 2),
+                  (4097, 4, 16), (4097, 8, 8), (4097, 16, 4)]
+
+
+@pytest.mark.parametrize("N,P,W", FULL_MULTIWAVE)
+def test_frozen_metric_every_full_lane_configuration(monkeypatch, N, P, W):
+    monkeypatch.setenv("ADSCL_TUNE", "%d:%dx%d" % (N, P, W))
+    n = 300
+    c = np.array([[0.8, -0.5, 0.25, 0.1]])
+    b = adscl.Batch([N], n_modes=4, flags=adscl.FROZEN_METRIC)
+    classes, cls = b.kernel_stats()
+    assert (classes[cls[0]]["P"], classes[cls[0]]["W"]) == (P, W)
+    b.init_modes(np.ones(1), c)
+    b.step(n, 1e9)
+    st = gpu_state(b)
+    Phi, Pi = O.init_modes(N, 1.0, c[0])
+    ref = O.evolve(Phi, Pi, n, frozen=True)
+    for f in ("Phi", "Pi"):
+        assert_close(st[f], ref[f], "frozen N=%d %dx%d %s" % (N, P, W, f))
+    b.close()
+
+
 def test_mode_data_and_spectrum():
     """Mode-sum initial data (32 modes, c_j ~ N(0,1) e^{-j/4}, eps=0.1) and the
     16-mode spectrum, at t = 0 and after 500 steps."""
