@@ -122,11 +122,19 @@ int adscl_get_state(adscl_ctx* ctx, double* Phi, double* Pi, double* A, double* 
  * collapse/non-finite (-1 if none), min A of the current state. */
 int adscl_status(adscl_ctx* ctx, double* t, int64_t* steps, int32_t* state, double* t_collapse, double* minA);
 
-/* Diagnostics of the current state (Sec. II: mass and constraint residuals),
- * out [n_inst x 4]: max_i |R_A'|, max_i |R_delta'| over interior points with
- * R_A' = D A - [(1+2 sin^2 x)/(sin x cos x)(1-A) - sin x cos x A (Phi^2+Pi^2)]
- * (Eq. (5)) and R_delta' = D delta + sin x cos x (Phi^2+Pi^2) (Eq. (6)), the
- * mass m(pi/2), and M = int tan^2 x A (Phi^2+Pi^2) dx by 4-point cell rule. */
+/* Diagnostics of the current state (Sec. II: mass and the residuals of the
+ * equations), out [n_inst x 5] row-major:
+ *   0: max_i |R_A'|,  R_A' = D A - [(1+2 sin^2 x)/(sin x cos x)(1-A)
+ *                               - sin x cos x A (Phi^2+Pi^2)]         (Eq. (5)),
+ *   1: max_i |R_delta'|, R_delta' = D delta + sin x cos x (Phi^2+Pi^2)   (Eq. (6)),
+ *   2: max_i |R_A_t|,  R_A_t = A_t + 2 sin x cos x A^2 e^-delta Phi Pi   (Eq. (4)),
+ *      A_t the derivative of the constraint solve of A in the direction of the
+ *      right-hand sides (Phi_t, Pi_t) of Eqs. (2)-(3) (the rate of change of A
+ *      along the semi-discrete flow); NaN with ADSCL_FROZEN_METRIC,
+ *   3: the mass m(pi/2),
+ *   4: M = int tan^2 x A (Phi^2+Pi^2) dx by the 4-point cell rule,
+ * maxima over interior points, D the 4th-order centred difference.  Holds
+ * 16 (sum N_b) bytes of device scratch in the context after the first call. */
 int adscl_constraints(adscl_ctx* ctx, double* out, int mem);
 
 /* Mode energies of the current state (Sec. II: decomposition into normal

@@ -25,7 +25,8 @@ RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
 
 # Every function include/adscl.h declares.
 EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
-           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_spectrum", "adscl_spectrum_snaps",
+           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints",
+           "adscl_spectrum", "adscl_spectrum_snaps",
            "adscl_adjoint", "adscl_descend", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error",
            "adscl_autotune", "adscl_autotune_clear")
 
@@ -262,7 +263,9 @@ class Batch:
         return dict(t=t, steps=steps, state=state, t_c=tc, minA=mA)
 
     def constraints(self):
-        out = np.zeros((self.n_inst, 4))
+        """[n_inst, 5]: max |R_A'|, max |R_delta'|, max |R_A_t| (Eqs. (5), (6), (4)),
+        the mass m(pi/2) and the mass integral (adscl_constraints)."""
+        out = np.zeros((self.n_inst, 5))
         self._check(lib().adscl_constraints(self._h, out.ctypes.data, MEM_HOST))
         return out
 

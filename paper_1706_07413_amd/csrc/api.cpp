@@ -1140,21 +1140,39 @@ int adscl_status(adscl_ctx* c, double* t, int64_t* steps, int32_t* state, double
     return ADSCL_OK;
 }
 
-int adscl_constraints(adscl_ctx* c, double* out, int mem)
+// The diagnostics of adscl_constraints with `scr` (2 * total + 5 * n_inst
+// doubles of device memory) as the residual kernel's scratch and the staging of
+// host outputs.
+static int constraints_call(adscl_ctx* c, double* scr, double* out, int mem)
+{
+    double* dst = mem == ADSCL_MEM_DEVICE ? out : scr + 2 * c->total;
+    const double* s = c->state5;
+    HIP_TRY(c, launch_diagnostics(c->n_inst, c->d_ic, s, s + c->total, s + 2 * c->total, s + 3 * c->total,
+                                  s + 4 * c->total, dst, c->stream));
+    const int frozen = (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0;
+    HIP_TRY(c, launch_adot_residual(c->n_inst, c->d_ic, s, c->total, frozen, c->ko, scr, dst, c->stream));
+    if (mem == ADSCL_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(out, dst, sizeof(double) * 5 * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return ADSCL_OK;
+}
+
+static int constraints_check(adscl_ctx* c, const double* out, int mem)
 {
     if (!c) return fail(nullptr, ADSCL_EINVAL, "ctx is NULL");
     if (!c->initialized) return fail(c, ADSCL_ESTATE, "adscl_constraints before any adscl_init*");
     if (!out) return fail(c, ADSCL_EINVAL, "out is NULL");
-    if (int rc = check_mem(c, mem)) return rc;
-    double* dst = mem == ADSCL_MEM_DEVICE ? out : c->d_tmp;
-    const double* s = c->state5;
-    HIP_TRY(c, launch_diagnostics(c->n_inst, c->d_ic, s, s + c->total, s + 2 * c->total, s + 3 * c->total,
-                                  s + 4 * c->total, dst, c->stream));
-    if (mem == ADSCL_MEM_HOST) {
-        HIP_TRY(c, hipMemcpyAsync(out, dst, sizeof(double) * 4 * c->n_inst, hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-    }
-    return ADSCL_OK;
+    return check_mem(c, mem);
+}
+
+int adscl_constraints(adscl_ctx* c, double* out, int mem)
+{
+    if (int rc = constraints_check(c, out, mem)) return rc;
+    void* scr;
+    if (int rc = buffer(c, "constraints", sizeof(double) * (2 * (size_t)c->total + 5 * (size_t)c->n_inst), &scr))
+        return rc;
+    return constraints_call(c, (double*)scr, out, mem);
 }
 
 // Spectra of n_slots states at `base` ([slot][5][total] on the device) into

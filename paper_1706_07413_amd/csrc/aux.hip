@@ -297,8 +297,8 @@ __device__ double block_reduce(double v, bool take_max, double* sh)
     return r;
 }
 
-// Residuals of Eqs. (5)-(6) at interior points and the mass integral of Sec. II.
-// One 256-thread block per instance.
+// Residuals of Eqs. (5)-(6) at interior points and the mass integral of Sec. II,
+// into columns 0, 1, 3, 4 of out [n_inst][5].  One 256-thread block per instance.
 __global__ void __launch_bounds__(256) diagnostics_kernel(int n_inst, const InstConst* ic, const double* Phi,
                                                           const double* Pi, const double* A,
                                                           const double* delta, const double* m, double* out)
@@ -351,10 +351,192 @@ __global__ void __launch_bounds__(256) diagnostics_kernel(int n_inst, const Inst
     rd = block_reduce(rd, true, sh);
     M = block_reduce(M, false, sh);
     if (threadIdx.x == 0) {
-        out[b * 4 + 0] = rA;
-        out[b * 4 + 1] = rd;
-        out[b * 4 + 2] = m[c.off + N - 1];
-        out[b * 4 + 3] = M;
+        out[b * 5 + 0] = rA;
+        out[b * 5 + 1] = rd;
+        out[b * 5 + 3] = m[c.off + N - 1];
+        out[b * 5 + 4] = M;
+    }
+}
+
+// Residual of Eq. (4), A_t = -2 sin x cos x A^2 e^-delta Phi Pi, which the
+// evolution never imposes (Sec. II monitors the residuals of its equations).
+// A_t is the time derivative of the discrete A of the constraint solve along
+// the semi-discrete flow: the derivative of A(Phi, Pi) in the direction of the
+// right-hand sides (Phi_t, Pi_t) of Eqs. (2)-(3), taken through each step of
+// the solve (q = Phi^2 + Pi^2, p = sin x cos x q, delta~ = -prefix cell rule of
+// p, E = e^-delta, sigma = tan^2 x q E, S = prefix cell rule of sigma,
+// m = S / E, A = 1 - cos^3 x / sin x m):
+//   q_t = 2 (Phi Phi_t + Pi Pi_t),  p_t = sin x cos x q_t,
+//   delta~_t = -prefix cell rule of p_t,  E_t = -E delta~_t,
+//   sigma_t = tan^2 x (q_t E + q E_t),  S_t = prefix cell rule of sigma_t,
+//   m_t = (S_t - m E_t) / E,  A_t = -cos^3 x / sin x m_t.
+// E is e^-delta of the gauge-shifted delta: m_t is homogeneous of degree 0 in
+// a constant factor of E, S and their derivatives, so the shift drops out.
+// Input: the packed state (Phi, Pi, A, delta, m) of the current step, whose
+// metric is the constraint solve of (Phi, Pi).  One 256-thread block per
+// instance, thread t owning a run of consecutive points; `scr` holds two
+// doubles per packed point: X = p_t for the whole kernel, Y = q_t of the own
+// points, then sigma_t (each thread overwrites only its own entries, and the
+// neighbours read Y only after the barrier that follows).  delta~_t is formed
+// twice from X with the same carry, so it needs no storage.
+// out[b*5 + 2] = max over interior points of |A_t + 2 sin x cos x A^2
+// e^-delta Phi Pi|; NaN with the metric frozen (A is then held, not solved).
+__global__ void __launch_bounds__(256) adot_residual_kernel(int n_inst, const InstConst* ic,
+                                                            const double* state5, int64_t total, int frozen,
+                                                            double ko, double* scr, double* out)
+{
+    __shared__ double sh[16];
+    const int b = blockIdx.x;
+    if (b >= n_inst) return;
+    const InstConst c = ic[b];
+    const int N = c.N;
+    const double h = c.h;
+    if (frozen) {
+        if (threadIdx.x == 0) out[b * 5 + 2] = __builtin_nan("");
+        return;
+    }
+    const double* Ph = state5 + c.off;
+    const double* Pq = state5 + total + c.off;
+    const double* Aa = state5 + 2 * total + c.off;
+    const double* dd = state5 + 3 * total + c.off;
+    const double* mm = state5 + 4 * total + c.off;
+    double* X = scr + c.off;
+    double* Y = scr + total + c.off;
+    const double kof = ko / (64.0 * h), i12h = 1.0 / (12.0 * h);
+    auto t2_at = [&](int i) -> double {
+        const double t = tan((double)i * h);
+        return t * t;
+    };
+    // Phi odd about 0, even about pi/2; Pi even about 0, odd about pi/2
+    auto phg = [&](int i) -> double {
+        if (i < 0) return -Ph[-i];
+        if (i > N - 1) return Ph[2 * (N - 1) - i];
+        return Ph[i];
+    };
+    auto pig = [&](int i) -> double {
+        if (i < 0) return Pq[-i];
+        if (i > N - 1) return -Pq[2 * (N - 1) - i];
+        return Pq[i];
+    };
+    auto w_at = [&](int i) -> double { return Aa[i] * exp(-dd[i]); };
+    // f1 = w Pi: even about 0, odd about pi/2
+    auto f1g = [&](int i) -> double {
+        if (i < 0) return w_at(-i) * Pq[-i];
+        if (i > N - 1) {
+            const int j = 2 * (N - 1) - i;
+            return -(w_at(j) * Pq[j]);
+        }
+        return w_at(i) * Pq[i];
+    };
+    // g = tan^2 x w Phi up to N - 2, the even 6th-order extrapolation at N - 1;
+    // odd about 0, even about pi/2
+    auto g_in = [&](int i) -> double {
+        if (i == N - 1) {
+            const double g2 = t2_at(N - 2) * (w_at(N - 2) * Ph[N - 2]);
+            const double g3 = t2_at(N - 3) * (w_at(N - 3) * Ph[N - 3]);
+            const double g4 = t2_at(N - 4) * (w_at(N - 4) * Ph[N - 4]);
+            return (15.0 * g2 - 6.0 * g3 + g4) / 10.0;
+        }
+        return t2_at(i) * (w_at(i) * Ph[i]);
+    };
+    auto gg = [&](int i) -> double {
+        if (i < 0) return -g_in(-i);
+        if (i > N - 1) return g_in(2 * (N - 1) - i);
+        return g_in(i);
+    };
+    auto ko7 = [&](auto&& u, int i) -> double {
+        return kof * (u(i - 3) - 6.0 * u(i - 2) + 15.0 * u(i - 1) - 20.0 * u(i) + 15.0 * u(i + 1) - 6.0 * u(i + 2)
+                      + u(i + 3));
+    };
+    auto d5 = [&](auto&& u, int i) -> double { return (u(i - 2) - 8.0 * u(i - 1) + 8.0 * u(i + 1) - u(i + 2)) * i12h; };
+
+    const int tid = threadIdx.x;
+    const int C = (N + 255) / 256;
+    const int i0 = tid * C;
+    const int i1 = min(N, i0 + C);
+    // right-hand sides of Eqs. (2)-(3) (pinned points 0 except Pi at the origin),
+    // q_t and p_t at the own points
+    for (int i = i0; i < i1; ++i) {
+        double rPh = 0.0, rPi = 0.0;
+        if (i >= 1 && i <= N - 2) {
+            const double t = tan((double)i * h);
+            rPh = d5(f1g, i) + ko7(phg, i);
+            rPi = (1.0 / (t * t)) * d5(gg, i) + ko7(pig, i);
+        } else if (i == 0) {
+            // lim tan^-2 x (tan^2 x f2)' = 3 f2'(0), f2 = w Phi odd about 0
+            const double f21 = w_at(1) * Ph[1], f22 = w_at(2) * Ph[2];
+            rPi = 3.0 * ((16.0 * f21 - 2.0 * f22) * i12h) + ko7(pig, 0);
+        }
+        const double qt = 2.0 * (Ph[i] * rPh + Pq[i] * rPi);
+        const double x = (double)i * h;
+        X[i] = (i == 0 || i == N - 1) ? 0.0 : sin(x) * cos(x) * qt;
+        Y[i] = qt;
+    }
+    __syncthreads();
+    // delta~_t: 0 at x = 0, minus the prefix cell rule of p_t (odd about both
+    // ends), in the prefix form of the sum of cells (for an odd u with u_0 = 0
+    // the terms -u_{-1} - 12 u_0 + u_1 are 2 u_1)
+    auto ptg = [&](int i) -> double {
+        double sg = 1.0;
+        if (i < 0) { i = -i; sg = -1.0; }
+        if (i > N - 1) { i = 2 * (N - 1) - i; sg = -sg; }
+        return sg * X[i];
+    };
+    double ps = 0.0;
+    for (int i = i0; i < i1; ++i) ps += X[i];
+    double tot;
+    const double carry = block_excl_scan(ps, sh, tot);
+    const double p1 = X[1];
+    auto dtil_t = [&](double Rk, int i) -> double {
+        return -(h / 24.0) * (24.0 * Rk - 12.0 * X[i] + ptg(i - 1) - ptg(i + 1) + 2.0 * p1);
+    };
+    double R = carry, ss = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        R += X[i];
+        const double E = exp(-dd[i]);
+        const double Et = -E * dtil_t(R, i);
+        const double q = Ph[i] * Ph[i] + Pq[i] * Pq[i];
+        const double sg = (i == 0 || i == N - 1) ? 0.0 : t2_at(i) * (Y[i] * E + q * Et);
+        Y[i] = sg;
+        ss += sg;
+    }
+    __syncthreads();
+    // S_t: 0 at x = 0, the prefix cell rule of sigma_t (even about both ends,
+    // 0 there); then m_t, A_t and the residual at interior points
+    auto sgg = [&](int i) -> double {
+        if (i < 0) i = -i;
+        if (i > N - 1) i = 2 * (N - 1) - i;
+        return Y[i];
+    };
+    double tot2;
+    const double carry2 = block_excl_scan(ss, sh + 4, tot2);
+    double R1 = carry, R2 = carry2, rmax = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        R1 += X[i];
+        R2 += Y[i];
+        if (i == 0 || i == N - 1) continue;
+        const double St = (h / 24.0) * (24.0 * R2 - 12.0 * Y[i] + sgg(i - 1) - sgg(i + 1));
+        const double E = exp(-dd[i]);
+        const double Et = -E * dtil_t(R1, i);
+        const double mt = (St - mm[i] * Et) / E;
+        const double x = (double)i * h;
+        const double sn = sin(x), co = cos(x);
+        const double At = -(co * co * co / sn) * mt;
+        const double r = At + 2.0 * (sn * co) * Aa[i] * Aa[i] * E * Ph[i] * Pq[i];
+        rmax = fmax(rmax, fabs(r));
+        if (!(r == r)) rmax = r;  // keep a NaN
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        const double o = __shfl_xor(rmax, d, 64);
+        rmax = (o == o) ? fmax(rmax, o) : o;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) sh[8 + (tid >> 6)] = rmax;
+    __syncthreads();
+    if (tid == 0) {
+        double r = 0.0;
+        for (int w = 0; w < 4; ++w) r = (sh[8 + w] == sh[8 + w]) ? fmax(r, sh[8 + w]) : sh[8 + w];
+        out[b * 5 + 2] = r;
     }
 }
 
@@ -419,6 +601,13 @@ hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi
                               const double* A, const double* delta, const double* m, double* out, hipStream_t s)
 {
     diagnostics_kernel<<<dim3(n_inst), dim3(256), 0, s>>>(n_inst, ic, Phi, Pi, A, delta, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adot_residual(int n_inst, const InstConst* ic, const double* state5, int64_t total, int frozen,
+                                double ko, double* scr, double* out, hipStream_t s)
+{
+    adot_residual_kernel<<<dim3(n_inst), dim3(256), 0, s>>>(n_inst, ic, state5, total, frozen, ko, scr, out);
     return hipGetLastError();
 }
 

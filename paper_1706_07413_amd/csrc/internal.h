@@ -118,6 +118,9 @@ hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, doub
 hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi, const double* Pi,
                               const double* A, const double* delta, const double* m, double* out,
                               hipStream_t s);
+// Residual of Eq. (4) into column 2 of out [n_inst][5]; scr: 2 * total doubles.
+hipError_t launch_adot_residual(int n_inst, const InstConst* ic, const double* state5, int64_t total, int frozen,
+                                double ko, double* scr, double* out, hipStream_t s);
 // Spectrum rows: one state of one instance, as element offsets of its Phi, Pi
 // and A rows from a common base, and its output row.
 struct SpecRow {

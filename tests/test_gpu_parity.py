@@ -195,8 +195,45 @@ def test_constraints_diagnostics_match_oracle():
         scale_A = np.max(np.abs((1 + 2 * np.sin(xi) ** 2) / sc * (1 - A[1:-1]))) + np.max(np.abs(sc * A[1:-1] * q))
         assert abs(out[i, 0] - np.max(np.abs(RA))) <= 1e-11 * scale_A
         assert abs(out[i, 1] - np.max(np.abs(Rd))) <= 1e-11 * scale_d
-        assert abs(out[i, 2] - b.split(st["m"])[i][-1]) == 0.0
-        assert abs(out[i, 3] - O.mass_paper(Phi, Pi, A)) <= 1e-12 * out[i, 3]
+        assert abs(out[i, 3] - b.split(st["m"])[i][-1]) == 0.0
+        assert abs(out[i, 4] - O.mass_paper(Phi, Pi, A)) <= 1e-12 * out[i, 4]
+
+
+def adot_scale(Phi, Pi, A, d, Ad):
+    """Size of the two terms whose difference is the Eq. (4) residual."""
+    x, _ = O.grid(len(Phi))
+    src = 2 * np.sin(x) * np.cos(x) * A ** 2 * np.exp(-d) * Phi * Pi
+    return np.max(np.abs(Ad)) + np.max(np.abs(src[1:-1]))
+
+
+@pytest.mark.parametrize("gauge", [O.GAUGE_BOUNDARY, O.GAUGE_ORIGIN])
+def test_adot_residual_matches_oracle(gauge):
+    """|R_A_t|: the residual of Eq. (4) with A_t the derivative of the constraint
+    solve along the right-hand sides, against the oracle's, after 150 steps of
+    Gaussian data on full-lane, ragged and multi-workgroup grids.  The residual
+    is a difference of two terms of size `scale`; both sides form each term to
+    rounding (relative 1e-14 over the prefix sums), so they agree within 1e-11
+    of that scale."""
+    Ns = [65, 257, 777, 1025, 4097, 6145]
+    rng = np.random.default_rng(11)
+    eps = rng.uniform(2.0, 6.0, len(Ns))
+    sig = rng.uniform(0.15, 0.3, len(Ns))
+    b = adscl.Batch(Ns, gauge=gauge, a_collapse=0.0)
+    b.init_gaussian(eps, sig)
+    b.step(150, 1e9)
+    st = gpu_state(b)
+    out = b.constraints()
+    for i, N in enumerate(Ns):
+        Phi, Pi, A, d = (b.split(st[f])[i] for f in ("Phi", "Pi", "A", "delta"))
+        Ad, R = O.adot_residual(Phi, Pi, gauge=gauge)
+        scale = adot_scale(Phi, Pi, A, d, Ad)
+        ref = np.max(np.abs(R[1:-1]))
+        assert abs(out[i, 2] - ref) <= 1e-11 * scale, (N, out[i, 2], ref, scale)
+        # the residual is small against its terms: Eq. (4) holds to truncation error
+        assert ref < 1e-3 * scale
+    fz = adscl.Batch([129], flags=adscl.FROZEN_METRIC, n_modes=2)
+    fz.init_modes(np.array([0.5]), np.array([[1.0, 0.3]]))
+    assert np.isnan(fz.constraints()[0, 2])
 
 
 def test_collapse_and_failure_states():
