@@ -137,6 +137,18 @@ int adscl_status(adscl_ctx* ctx, double* t, int64_t* steps, int32_t* state, doub
  * 16 (sum N_b) bytes of device scratch in the context after the first call. */
 int adscl_constraints(adscl_ctx* ctx, double* out, int mem);
 
+/* adscl_constraints for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, bit for bit, with their scratch in a fixed device array
+ * of the library (2^21 doubles, 16 MiB per GPU, held until the process ends)
+ * instead of a buffer the context allocates; no hipMalloc, hipFree or other
+ * allocating call.  Limit: 2 sum N_b + 5 n_inst <= 2^21 (ADSCL_EINVAL
+ * otherwise, before any work is enqueued).  Host `out` still synchronises the
+ * stream (use device `out` under capture).  Every call on one GPU shares that
+ * array: calls that overlap on the same GPU (different streams or threads)
+ * race and must be serialised by the caller. */
+int adscl_constraints_noalloc(adscl_ctx* ctx, double* out, int mem);
+
 /* Mode energies of the current state (Sec. II: decomposition into normal
  * modes), J <= n_modes, outputs [n_inst x J] (any may be NULL):
  * Pihat_j = sum_i h tan^2 x_i e_j(x_i) sqrt(A_i) Pi_i,

@@ -25,7 +25,7 @@ RUNNING, COLLAPSED, NONFINITE, DONE = 0, 1, 2, 3
 
 # Every function include/adscl.h declares.
 EXPORTS = ("adscl_create", "adscl_destroy", "adscl_init", "adscl_init_gaussian", "adscl_init_modes",
-           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints",
+           "adscl_step", "adscl_get_state", "adscl_status", "adscl_constraints", "adscl_constraints_noalloc",
            "adscl_spectrum", "adscl_spectrum_snaps",
            "adscl_adjoint", "adscl_descend", "adscl_sync", "adscl_layout", "adscl_kernel_stats", "adscl_last_error",
            "adscl_autotune", "adscl_autotune_clear")
@@ -73,6 +73,7 @@ def lib():
         "adscl_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int]),
         "adscl_status": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "adscl_constraints": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+        "adscl_constraints_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
         "adscl_spectrum": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_int]),
         "adscl_spectrum_snaps": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_int]),
         "adscl_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _d, _i32, _vp, _vp, _vp, ctypes.c_int]),
@@ -267,6 +268,17 @@ class Batch:
         the mass m(pi/2) and the mass integral (adscl_constraints)."""
         out = np.zeros((self.n_inst, 5))
         self._check(lib().adscl_constraints(self._h, out.ctypes.data, MEM_HOST))
+        return out
+
+    def constraints_noalloc(self, out=None):
+        """adscl_constraints_noalloc into `out` ([n_inst, 5] numpy or torch float64),
+        a new numpy array by default."""
+        if out is None:
+            out = np.zeros((self.n_inst, 5))
+        p, m = _ptr_mem(out)
+        self._check(lib().adscl_constraints_noalloc(self._h, p, m))
+        if m == MEM_DEVICE:
+            self.sync()
         return out
 
     def spectrum(self, J):

@@ -825,6 +825,9 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     } while (0)
 
     TRY_C(hipGetDevice(&c->device));
+    // address of this device's fixed scratch (adscl_constraints_noalloc), looked
+    // up once per device while it is current
+    TRY_C(static_scratch_init(c->device));
     int lds = 0;
     TRY_C(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     c->max_lds = (size_t)lds;
@@ -1173,6 +1176,19 @@ int adscl_constraints(adscl_ctx* c, double* out, int mem)
     if (int rc = buffer(c, "constraints", sizeof(double) * (2 * (size_t)c->total + 5 * (size_t)c->n_inst), &scr))
         return rc;
     return constraints_call(c, (double*)scr, out, mem);
+}
+
+int adscl_constraints_noalloc(adscl_ctx* c, double* out, int mem)
+{
+    if (int rc = constraints_check(c, out, mem)) return rc;
+    const size_t need = 2 * (size_t)c->total + 5 * (size_t)c->n_inst;
+    if (need > kStaticScratchDoubles)
+        return fail(c, ADSCL_EINVAL,
+                    "adscl_constraints_noalloc: 2 * sum N_b + 5 * n_inst = " + std::to_string(need) +
+                        " exceeds the fixed scratch of " + std::to_string(kStaticScratchDoubles) + " doubles");
+    double* scr = static_scratch(c->device);
+    if (!scr) return fail(c, ADSCL_ESTATE, "adscl_constraints_noalloc: no fixed scratch on this device");
+    return constraints_call(c, scr, out, mem);
 }
 
 // Spectra of n_slots states at `base` ([slot][5][total] on the device) into

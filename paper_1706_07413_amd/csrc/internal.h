@@ -121,6 +121,14 @@ hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi
 // Residual of Eq. (4) into column 2 of out [n_inst][5]; scr: 2 * total doubles.
 hipError_t launch_adot_residual(int n_inst, const InstConst* ic, const double* state5, int64_t total, int frozen,
                                 double ko, double* scr, double* out, hipStream_t s);
+
+// Fixed device scratch of the allocation-free entry point: 2^21 doubles
+// (16 MiB) per GPU, held until the process ends.  static_scratch_init looks up
+// its address on `device`, which must be the current device (once per device;
+// later calls return at once); static_scratch returns it, or NULL before that.
+constexpr size_t kStaticScratchDoubles = (size_t)1 << 21;
+hipError_t static_scratch_init(int device);
+double* static_scratch(int device);
 // Spectrum rows: one state of one instance, as element offsets of its Phi, Pi
 // and A rows from a common base, and its output row.
 struct SpecRow {
