@@ -74,6 +74,21 @@ typedef struct {
     int32_t gauge;           /* ADSCL_GAUGE_*                                         */
     int32_t n_modes;         /* largest J for adscl_spectrum / adscl_init_modes, <=128 */
     int32_t flags;           /* ADSCL_FROZEN_METRIC or 0                              */
+    /* Scheme options of Sec. II (the paper offers Runge-Kutta of order 2, 3 and
+     * 4 and uses 3; and evolving A by Eq. (4) instead of solving Eq. (5) at
+     * every stage, with a periodic re-integration of A from Eq. (5)):
+     * rk_order: 4 (or 0) classical RK4; 3 and 2 the strong-stability-preserving
+     *   methods of Shu and Osher (U1 = U + dt F(U), U2 = 3U/4 + (U1 + dt F(U1))/4,
+     *   U' = U/3 + 2(U2 + dt F(U2))/3; RK2: U' = U/2 + (U1 + dt F(U1))/2).
+     * a_reint: 0 solves A from Eq. (5) at every stage; K >= 1 evolves A with
+     *   Eq. (4), A_t = -2 sin x cos x A^2 e^-delta Phi Pi (delta from Eq. (6) at
+     *   every stage), and replaces it by Eq. (5)'s solution at the start of every
+     *   step that is a multiple of K; collapse is then tested on the evolved A,
+     *   which adscl_get_state returns (delta and m come from the constraints).
+     * Other than (4, 0): EINVAL with ADSCL_FROZEN_METRIC and a_reint > 0,
+     * EUNSUPPORTED for N_b > 4097 and for adscl_adjoint / adscl_descend. */
+    int32_t rk_order;
+    int32_t a_reint;
 } adscl_config;
 
 /* Create a context on the current HIP device.  `hip_stream` is a hipStream_t

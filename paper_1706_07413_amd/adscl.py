@@ -40,7 +40,8 @@ class AdsclError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("n_inst", ctypes.c_int32), ("n_grid", ctypes.POINTER(ctypes.c_int32)),
                 ("cfl", ctypes.c_double), ("ko_sigma", ctypes.c_double), ("a_collapse", ctypes.c_double),
-                ("gauge", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("gauge", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("rk_order", ctypes.c_int32), ("a_reint", ctypes.c_int32)]
 
 
 _lib = None
@@ -157,11 +158,14 @@ class Batch:
     """A batch of independent instances with grid sizes ``n_grid`` on one GPU."""
 
     def __init__(self, n_grid, cfl=0.25, ko_sigma=0.5, a_collapse=0.01, gauge=GAUGE_BOUNDARY, n_modes=0,
-                 flags=0, stream=None):
+                 flags=0, stream=None, rk_order=4, a_reint=0):
+        """``rk_order`` (4, 3 or 2) and ``a_reint`` (0: A from Eq. (5) at every
+        stage; K: A evolved by Eq. (4), re-integrated every K steps) select the
+        scheme options of adscl_config."""
         L = lib()
         self._N = np.ascontiguousarray(np.asarray(n_grid, dtype=np.int32))
         cfg = Config(len(self._N), self._N.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cfl, ko_sigma,
-                     a_collapse, gauge, n_modes, flags)
+                     a_collapse, gauge, n_modes, flags, rk_order, a_reint)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

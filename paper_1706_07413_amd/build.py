@@ -16,11 +16,12 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadscl.so")
 ARCH = os.environ.get("ADSCL_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["evolve.hip", "evolve_big.hip", "adjoint.hip", "aux.hip", "spectrum.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["evolve.hip", "evolve_big.hip", "adjoint.hip", "aux.hip", "spectrum.hip", "noalloc.hip", "scheme.hip", "api.cpp"]
 # The forward kernel is latency-bound (one workgroup of two wavefronts per SIMD
 # on a CU at P = 8): the machine scheduler's maximum-ILP strategy shortens its
 # dependent chains without spilling (1-2% on a step, same arithmetic).
-EXTRA = {"evolve.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+EXTRA = {"evolve.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+         "scheme.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def hipcc():

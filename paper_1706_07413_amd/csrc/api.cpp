@@ -65,6 +65,7 @@ struct adscl_ctx {
     int64_t max_N = 0;
     double cfl = 0.25, ko = 0.5, thr = 0.01;
     int gauge = 0, n_modes = 0, flags = 0;
+    int rk = 4, a_reint = 0;    // scheme options (adscl_config.rk_order, a_reint)
     size_t max_lds = 0;
 
     double* state5 = nullptr;   // [5][total]: Phi, Pi, A, delta, m
@@ -120,11 +121,20 @@ thread_local ClassCfg g_force{0, 0};
 const ClassCfg kAllClasses[] = {{4, 1}, {4, 2}, {4, 4},  {4, 8},  {4, 16}, {8, 1},
                                 {8, 2}, {8, 4}, {8, 8}, {16, 1}, {16, 2}, {16, 4}};
 
+// The smallest lane capacity 64 W P of the default configurations that holds
+// the N-1 evolved points, taking P = 8 over W = 8 at 2048 points (four
+// wavefronts, one per SIMD, so that two instances can share a compute unit).
+ClassCfg default_class(int N)
+{
+    static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {8, 8}};
+    for (const ClassCfg& c : pref)
+        if (64 * c.W * c.P >= N - 1) return c;
+    return ClassCfg{0, 0};
+}
+
 // Kernel configuration for grid size N: ADSCL_TUNE="N:PxW,..." if it names one
 // for N, else the configuration a tuning trial forces, else the autotuner's
-// choice for N, else the smallest lane capacity 64 W P that holds the N-1
-// evolved points, taking P = 8 over W = 8 at 2048 points (four wavefronts, one
-// per SIMD, so that two instances can share a compute unit).
+// choice for N, else default_class(N).
 ClassCfg choose_class(int N)
 {
     if (const char* t = std::getenv("ADSCL_TUNE")) {
@@ -147,10 +157,7 @@ ClassCfg choose_class(int N)
         auto it = g_tuned.find(N);
         if (it != g_tuned.end()) return it->second;
     }
-    static const ClassCfg pref[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {8, 8}};
-    for (const ClassCfg& c : pref)
-        if (64 * c.W * c.P >= N - 1) return c;
-    return ClassCfg{0, 0};
+    return default_class(N);
 }
 
 // Chunk configuration for a grid too large for one workgroup: (4, 8), i.e.
@@ -336,6 +343,10 @@ int run_classes(adscl_ctx* c, F&& launch)
     return ADSCL_OK;
 }
 
+// Whether the context uses a scheme option other than classical RK4 with A
+// solved at every stage.
+bool scheme(const adscl_ctx* c) { return c->rk != 4 || c->a_reint > 0; }
+
 EvolveArgs evolve_args(adscl_ctx* c, int32_t snap_every)
 {
     EvolveArgs a;
@@ -357,7 +368,7 @@ EvolveArgs evolve_args(adscl_ctx* c, int32_t snap_every)
     a.frozen = (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0;
     a.ckpt_every = 0;
     a.src_every = 1;
-    a.pad = 0;
+    a.a_reint = c->a_reint;
     return a;
 }
 
@@ -387,7 +398,9 @@ int run_evolve(adscl_ctx* c, const EvolveArgs& base, bool timing = true)
         a.order = lc.d_order;
         hipError_t e = hipSuccess;
         if (timing && lc.t0 && (e = hipEventRecord(lc.t0, s)) != hipSuccess) return e;
-        if ((e = launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s)) != hipSuccess) return e;
+        e = scheme(c) ? launch_evolve_scheme(lc.cfg, c->rk, c->a_reint > 0, lc.full, (int)lc.inst.size(), a, s)
+                      : launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s);
+        if (e != hipSuccess) return e;
         if (timing && lc.t1) {
             if ((e = hipEventRecord(lc.t1, s)) != hipSuccess) return e;
             lc.timed = true;
@@ -402,7 +415,7 @@ int run_finalize(adscl_ctx* c, bool final, int32_t snap_every, int32_t n_slots, 
 {
     HIP_TRY(c, launch_finalize(c->n_inst, c->d_ic, c->d_status, c->state5, c->total, c->gauge,
                                (c->flags & ADSCL_FROZEN_METRIC) ? 1 : 0, c->thr, final, snap_every, n_slots,
-                               snaps, c->stream));
+                               snaps, c->stream, c->a_reint));
     return ADSCL_OK;
 }
 
@@ -697,6 +710,7 @@ int check_adjoint_args(adscl_ctx* c, const double* eps, const double* coef, int3
 {
     if (!eps || !coef) return fail(c, ADSCL_EINVAL, "NULL argument");
     if (c->flags & ADSCL_FROZEN_METRIC) return fail(c, ADSCL_EUNSUPPORTED, "adjoint needs the dynamic metric");
+    if (scheme(c)) return fail(c, ADSCL_EUNSUPPORTED, "adjoint of classical RK4 with A solved at every stage only");
     if (c->n_big > 0) return fail(c, ADSCL_EUNSUPPORTED, "adjoint supports N <= 4097");
     if (Jc < 1 || Jc > c->n_modes || J < 1 || J > c->n_modes)
         return fail(c, ADSCL_EINVAL, "need 1 <= Jc, J <= n_modes");
@@ -739,6 +753,8 @@ double tune_trial(int N, ClassCfg cfg, int n_inst, int steps, std::string& err)
     c.gauge = ADSCL_GAUGE_BOUNDARY;
     c.n_modes = 1;
     c.flags = 0;
+    c.rk_order = 4;
+    c.a_reint = 0;
     adscl_ctx* ctx = nullptr;
     int rc = adscl_create(&c, nullptr, &ctx);
     g_force_N = 0;
@@ -791,6 +807,17 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     if (cfg->gauge != ADSCL_GAUGE_BOUNDARY && cfg->gauge != ADSCL_GAUGE_ORIGIN) return fail(nullptr, ADSCL_EINVAL, "bad gauge");
     if (cfg->n_modes < 0 || cfg->n_modes > 128) return fail(nullptr, ADSCL_EINVAL, "n_modes must be in [0, 128]");
     if (cfg->flags & ~(ADSCL_FROZEN_METRIC | ADSCL_TIME_KERNELS)) return fail(nullptr, ADSCL_EINVAL, "unknown flags");
+    if (cfg->rk_order != 0 && cfg->rk_order != 2 && cfg->rk_order != 3 && cfg->rk_order != 4)
+        return fail(nullptr, ADSCL_EINVAL, "rk_order must be 0, 2, 3 or 4");
+    if (cfg->a_reint < 0) return fail(nullptr, ADSCL_EINVAL, "a_reint must be >= 0");
+    if (cfg->a_reint > 0 && (cfg->flags & ADSCL_FROZEN_METRIC))
+        return fail(nullptr, ADSCL_EINVAL, "an evolved A (a_reint > 0) needs the dynamic metric");
+    const int rk_order = cfg->rk_order == 0 ? 4 : cfg->rk_order;
+    if (rk_order != 4 || cfg->a_reint > 0)
+        for (int b = 0; b < cfg->n_inst; ++b)
+            if (cfg->n_grid[b] > kMaxOneGroup)
+                return fail(nullptr, ADSCL_EUNSUPPORTED,
+                            "the scheme options (rk_order != 4 or a_reint > 0) support N <= 4097");
 
     adscl_ctx* c = new adscl_ctx();
     c->n_inst = cfg->n_inst;
@@ -809,6 +836,8 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     c->gauge = cfg->gauge;
     c->n_modes = cfg->n_modes;
     c->flags = cfg->flags;
+    c->rk = rk_order;
+    c->a_reint = cfg->a_reint;
 
     auto bail = [&](int code) {
         g_create_error = c->err;
@@ -908,7 +937,7 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
         }
         if (!c->tables.count(N)) {
             NTables t;
-            t.cfg = choose_class(N);
+            t.cfg = scheme(c) ? default_class(N) : choose_class(N);
             if (t.cfg.P == 0) {
                 c->err = "no kernel configuration for N=" + std::to_string(N);
                 return bail(ADSCL_EUNSUPPORTED);
@@ -918,7 +947,8 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
                          " B of LDS, device allows " + std::to_string(c->max_lds);
                 return bail(ADSCL_EUNSUPPORTED);
             }
-            TRY_C(prepare_evolve(t.cfg, c->max_lds));
+            if (scheme(c)) TRY_C(prepare_evolve_scheme(t.cfg, c->rk, c->a_reint > 0, c->max_lds));
+            else TRY_C(prepare_evolve(t.cfg, c->max_lds));
             TRY_C(prepare_adjoint(t.cfg, c->max_lds));
             std::vector<double> tab, e, wpi, wphi;
             host_tables(N, t.cfg, tab);
@@ -963,8 +993,10 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
         }
     }
     if (c->classes.size() > 1) TRY_C(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
-    // launch the biggest classes first (large instances last: they run after
-    // the others, on the context stream)
+    // one-workgroup classes by lane capacity, largest first (their launch
+    // order); large instances are listed last, but run_evolve launches them
+    // first, one after another on the context stream, before it forks the
+    // one-workgroup classes onto their streams: the two never overlap
     std::stable_sort(c->classes.begin(), c->classes.end(), [](const LaunchClass& x, const LaunchClass& y) {
         if ((x.chunks > 0) != (y.chunks > 0)) return y.chunks > 0;
         return 64 * x.cfg.W * x.cfg.P > 64 * y.cfg.W * y.cfg.P;

@@ -113,14 +113,16 @@ struct FinArgs {
     int32_t gauge;
     int32_t frozen;
     int32_t final_;
-    int32_t pad;
+    int32_t a_reint;  // > 0: A is evolved; the state's A is kept unless steps % a_reint == 0
 };
 
 // Constraint solve of the packed state of one instance per 256-thread block
 // (Sec. II, Eqs. (5)-(6), the same discretisation as the evolution kernel:
 // 4-point cell rule in prefix-sum form, m = (1 - A) sin x / cos^3 x), written
 // out as (Phi, Pi, A, delta, m); then min A, the mass m(pi/2) and, at the end
-// of a call, the collapse / non-finite test of the final state.
+// of a call, the collapse / non-finite test of the final state.  With A evolved
+// (a_reint > 0) the state's A is kept (and tested) except at steps that are a
+// multiple of a_reint, where the solve's A replaces it as the evolution would.
 __global__ void __launch_bounds__(256) finalize_kernel(FinArgs f)
 {
     __shared__ double sh[16];
@@ -188,6 +190,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs f)
     };
     double mn = 1.0, chk = 0.0;
     int col = 0;
+    const bool keepA = f.a_reint > 0 && (st.steps % f.a_reint) != 0;
+    const double* Arow = f.state5 + 2 * f.total + c.off;
     if (!f.frozen) {
         double ss = 0.0;
         for (int i = i0; i < i1; ++i) ss += sig_at(i);
@@ -201,7 +205,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinArgs f)
             const double E = exp(-dl);
             const double m = S / E;
             double A = 1.0;
-            if (i >= 1 && i <= N - 2) {
+            if (keepA) {
+                A = Arow[i];
+                if (A < f.a_collapse) col = 1;
+            } else if (i >= 1 && i <= N - 2) {
                 const double x = (double)i * h;
                 const double s = sin(x), co = cos(x);
                 const double c3s = co * co * co / s;
@@ -578,7 +585,7 @@ hipError_t launch_set_targets(int n_inst, const InstConst* ic, InstStatus* st, i
 
 hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, double* state5, int64_t total,
                            int gauge, int frozen, double a_collapse, bool final, int32_t snap_every,
-                           int32_t n_slots, double* snaps, hipStream_t s)
+                           int32_t n_slots, double* snaps, hipStream_t s, int32_t a_reint)
 {
     FinArgs f;
     f.ic = ic;
@@ -592,7 +599,7 @@ hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, doub
     f.gauge = gauge;
     f.frozen = frozen;
     f.final_ = final ? 1 : 0;
-    f.pad = 0;
+    f.a_reint = a_reint;
     finalize_kernel<<<dim3(n_inst), dim3(256), 0, s>>>(f);
     return hipGetLastError();
 }

@@ -59,7 +59,7 @@ struct EvolveArgs {
     int32_t frozen;
     int32_t ckpt_every;
     int32_t src_every;
-    int32_t pad;
+    int32_t a_reint;        // A evolved by Eq. (4), re-integrated every a_reint steps (0: solved)
 };
 
 // A kernel configuration: P grid points per lane, W wavefronts per instance.
@@ -77,6 +77,12 @@ size_t evolve_lds_bytes(ClassCfg c);
 hipError_t prepare_evolve(ClassCfg c, size_t max_lds);
 // full: every instance of the launch has N - 1 == 64 W P.
 hipError_t launch_evolve(ClassCfg c, bool full, int n_blocks, const EvolveArgs& a, hipStream_t s);
+// The scheme variants (scheme.hip): RK order 2 or 3 (A solved or evolved), or
+// 4 with A evolved (eva), on the configurations scheme_class_supported accepts.
+bool scheme_class_supported(ClassCfg c);
+hipError_t prepare_evolve_scheme(ClassCfg c, int rk, bool eva, size_t max_lds);
+hipError_t launch_evolve_scheme(ClassCfg c, int rk, bool eva, bool full, int n_blocks, const EvolveArgs& a,
+                                hipStream_t s);
 
 // One large instance over `chunks` workgroups of a (P, W) chunk class
 // (cooperative launch): its index, the exchange records [chunks][32], and an
@@ -113,7 +119,7 @@ hipError_t launch_set_targets(int n_inst, const InstConst* ic, InstStatus* st, i
 // and marked DONE at n_final.
 hipError_t launch_finalize(int n_inst, const InstConst* ic, InstStatus* st, double* state5, int64_t total,
                            int gauge, int frozen, double a_collapse, bool final, int32_t snap_every,
-                           int32_t n_slots, double* snaps, hipStream_t s);
+                           int32_t n_slots, double* snaps, hipStream_t s, int32_t a_reint = 0);
 // Diagnostics: out[b*4 + {0..3}] = max|R_A'|, max|R_delta'|, m(pi/2), M (cell rule).
 hipError_t launch_diagnostics(int n_inst, const InstConst* ic, const double* Phi, const double* Pi,
                               const double* A, const double* delta, const double* m, double* out,

@@ -498,6 +498,66 @@ struct Stage {
         }
     }
 
+    // The first prefix sum of the constraint solve alone (Eq. (6)): delta (gauge
+    // applied) and e^{-delta} at own points and the delta~ end value dN, for
+    // stages whose A is evolved with Eq. (4) instead of solved from Eq. (5).
+    // Contains barrier B1.
+    __device__ __forceinline__ void delta_scan(const double* q, double* dl, double* E, double& dN)
+    {
+        const auto tb = tables();
+        double p[P];
+        double ptot = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            p[k] = tab(tb, 0, k) * q[k];  // table is 0 off 1..N-2
+            ptot += p[k];
+        }
+        const double incl = wave_incl_scan(ptot);
+        if (lane == 63) red[wv] = incl;
+        if constexpr (EDGE) {
+            if (lane == 0) XP[2 * (wv + 1)] = p[0];
+            if (lane == 63) XP[2 * (wv + 1) + 1] = p[P - 1];
+            if (tid == 0) XP[1] = -p[1];                // p_{-1} = -p_1
+            if (tid == NL - 1) XP[2 * (W + 1)] = 0.0;  // p_{N-1} = 0
+        } else {
+            PE[tid] = p[0];
+            PE[NL + tid] = p[P - 1];
+        }
+        if (tid == 0) red[4 * W] = p[1];
+        if (FULL) {
+            if (tid == NL - 1) red[4 * W + 1] = p[P - 1];
+        } else if (has_nm2) {
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                if (i0 + k == N - 2) red[4 * W + 1] = p[k];
+        }
+        __syncthreads();  // B1
+        double carry, tot;
+        wave_totals(red, carry, tot);
+        carry += incl - ptot;
+        const double p1 = red[4 * W], pN2 = red[4 * W + 1];
+        double pl, pr;
+        if constexpr (EDGE) {
+            pl = dpp_old<0x138>(XP[2 * wv + 1], p[P - 1]);
+            pr = dpp_old<0x130>(XP[2 * (wv + 2)], p[0]);
+        } else {
+            pl = (tid > 0) ? PE[NL + tid - 1] : -p1;
+            pr = (tid < NL - 1) ? PE[tid + 1] : 0.0;
+        }
+        dN = -h24 * (24.0 * tot + 2.0 * pN2 + 2.0 * p1);
+        const double shift = bgauge ? dN : 0.0;
+        double R = carry;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            R += p[k];
+            const double pm = (k == 0) ? pl : p[k - 1];
+            const double pp = (k == P - 1) ? pr : p[k + 1];
+            const double dtil = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp + 2.0 * p1);
+            dl[k] = dtil - shift;
+            E[k] = exp_tab(-dl[k], X64);
+        }
+    }
+
     // Right-hand sides of Eqs. (2)-(3) at the published stage input: barrier B0,
     // Kreiss-Oliger terms and q from the +-3 window, the constraint solve (B1,
     // B2), the fluxes f1 = A e^-delta Pi, g = tan^2 x A e^-delta Phi with parity
@@ -509,11 +569,18 @@ struct Stage {
     // stores e^-delta and S of the lane's points to fields fE and fE + 1 of ES.
     // v0, v1: the published stage input of the own points (read on the edge
     // path, where it is not in LDS).
-    template <bool KEEP = false>
+    // EVA (A evolved by Eq. (4), the paper's alternative to solving Eq. (5) at
+    // every stage): the stage's A of the own points is `av`; only the first
+    // prefix sum runs (delta from Eq. (6)), the fluxes take w = av e^-delta, the
+    // collapse test is av < thr; with `reint` the full solve runs instead and
+    // its A, 1 - cos^3 x/sin x S/e^-delta, replaces `av` (re-integration from
+    // Eq. (5)).  `wout` receives w = A e^-delta of the own points.
+    template <bool KEEP = false, bool EVA = false>
     __device__ __forceinline__ int rhs(bool check, bool frozen, const double* v0, const double* v1, double* r0,
-                                       double* r1, ADSCL_GLOBAL double* ES = nullptr, int fE = 0)
+                                       double* r1, ADSCL_GLOBAL double* ES = nullptr, int fE = 0,
+                                       double* av = nullptr, double* wout = nullptr, bool reint = false)
     {
-        if constexpr (EDGE) return rhs_edge<KEEP>(check, frozen, v0, v1, r0, r1, ES, fE);
+        if constexpr (EDGE) return rhs_edge<KEEP, EVA>(check, frozen, v0, v1, r0, r1, ES, fE, av, wout, reint);
         __syncthreads();  // B0
         const auto tb = tables();
         double ko0[P], ko1[P], q[P];
@@ -539,7 +606,13 @@ struct Stage {
         double dl[P], E[P], S[P];
         double dN = 0.0, tot2 = 0.0;
         if (!frozen) {
-            constraints(q, dl, E, S, dN, tot2);
+            if (EVA && !reint) {
+                delta_scan(q, dl, E, dN);
+#pragma unroll
+                for (int k = 0; k < P; ++k) S[k] = 0.0;
+            } else {
+                constraints(q, dl, E, S, dN, tot2);
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
@@ -564,7 +637,14 @@ struct Stage {
             if (own(k)) {
                 const double2 v = U[k * RS + col];
                 const double c3s = tab(tb, 2, k) * tab(tb, 0, k);
-                const double wk = E[k] - c3s * S[k];
+                double wk;
+                if constexpr (EVA) {
+                    if (reint) av[k] = 1.0 - c3s * (S[k] / E[k]);
+                    wk = av[k] * E[k];
+                    wout[k] = wk;
+                } else {
+                    wk = E[k] - c3s * S[k];
+                }
                 const double f1 = wk * v.y;
                 const double f2 = wk * v.x;
                 const double g = tab(tb, 1, k) * f2;
@@ -659,9 +739,10 @@ struct Stage {
     // with the metric frozen, when B3 is a stage's only barrier; the scan slots
     // (XP, XS) are written before B1 / B2 and read after them, with B3 between
     // a stage's reads and the next stage's writes.
-    template <bool KEEP>
+    template <bool KEEP, bool EVA>
     __device__ __forceinline__ int rhs_edge(bool check, bool frozen, const double* v0, const double* v1, double* r0,
-                                            double* r1, ADSCL_GLOBAL double* ES, int fE)
+                                            double* r1, ADSCL_GLOBAL double* ES, int fE, double* av, double* wout,
+                                            bool reint)
     {
         const auto tb = tables();
         double q[P];
@@ -670,7 +751,13 @@ struct Stage {
         double dl[P], E[P], S[P];
         double dN = 0.0, tot2 = 0.0;
         if (!frozen) {
-            constraints(q, dl, E, S, dN, tot2);
+            if (EVA && !reint) {
+                delta_scan(q, dl, E, dN);
+#pragma unroll
+                for (int k = 0; k < P; ++k) S[k] = 0.0;
+            } else {
+                constraints(q, dl, E, S, dN, tot2);
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
@@ -688,7 +775,14 @@ struct Stage {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const double c3s = tab(tb, 2, k) * tab(tb, 0, k);
-            const double wk = E[k] - c3s * S[k];
+            double wk;
+            if constexpr (EVA) {
+                if (reint) av[k] = 1.0 - c3s * (S[k] / E[k]);
+                wk = av[k] * E[k];
+                wout[k] = wk;
+            } else {
+                wk = E[k] - c3s * S[k];
+            }
             const double f2 = wk * v0[k];
             ff[k] = wk * v1[k];
             fg[k] = tab(tb, 1, k) * f2;

@@ -55,6 +55,17 @@ def test_create_rejects_bad_parameters(field, value):
     assert L.adscl_create(None, None, ctypes.byref(h)) == adscl.EINVAL
 
 
+@pytest.mark.parametrize("rk,K,flags,N,code", [(5, 0, 0, 65, -1), (1, 0, 0, 65, -1), (3, -1, 0, 65, -1),
+                                               (4, 8, 1, 65, -1), (3, 0, 0, 16385, -5), (4, 4, 0, 8193, -5)])
+def test_create_rejects_bad_scheme_options_before_touching_the_gpu(rk, K, flags, N, code):
+    L = adscl.lib()
+    Ns = np.asarray([N], np.int32)
+    cfg = adscl.Config(1, Ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0.25, 0.5, 0.01, 0, 0, flags, rk, K)
+    h = ctypes.c_void_p()
+    assert L.adscl_create(ctypes.byref(cfg), None, ctypes.byref(h)) == code
+    assert h.value is None
+
+
 def test_null_context_calls_fail_cleanly():
     L = adscl.lib()
     assert L.adscl_sync(None) == adscl.EINVAL
