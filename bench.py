@@ -76,7 +76,27 @@ def pt_steps(N, steps):
     return float(np.sum(np.asarray(N, np.float64) * np.asarray(steps, np.float64)))
 
 
-def adjoint_rate(adscl, T, iters=2):
+def adjoint_config3(adscl):
+    """One gradient of the single-instance adjoint workload at its stated size
+    (N = 4097, 32 mode coefficients, eps = 0.1, T = 100: 1 043 038 steps,
+    drift of 16 mode energies, checkpoints every 512 steps)."""
+    import torch
+    from paper_1706_07413_amd import inputs as I
+    cfg = I.config3()
+    b = adscl.Batch(cfg["N"], gauge=cfg["gauge"], a_collapse=cfg["a_collapse"], n_modes=32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, g, v = b.adjoint(cfg["eps"], cfg["c"], cfg["J_obj"], cfg["T"], cfg["ckpt_every"])
+    dt = time.perf_counter() - t0
+    st = b.status()
+    b.close()
+    return {"workload": "adjoint_N4097: one instance, 32 modes, eps 0.1, T=100 (%d steps), J_obj 16, K 512"
+                        % int(st["steps"][0]),
+            "grads_per_s": 1.0 / dt, "s_per_gradient": dt, "valid": int(v[0]), "L": float(L[0]),
+            "forward_pt_steps": float(cfg["N"][0]) * float(st["steps"][0])}
+
+
+def adjoint_rate(adscl, T, iters=2, warmup=1):
     """Gradients per second of the batched descent loop: the 256-instance
     mode-data draw (N in {2049, 4097}, 32 modes, drift of 16 modes,
     checkpoints every 512 steps) over a window of T time units; each iteration
@@ -88,7 +108,8 @@ def adjoint_rate(adscl, T, iters=2):
     b = adscl.Batch(cfg["N"], gauge=cfg["gauge"], a_collapse=cfg["a_collapse"], n_modes=32)
     eps = torch.tensor(cfg["eps"], dtype=torch.float64, device="cuda")
     c = torch.tensor(cfg["c"], dtype=torch.float64, device="cuda")
-    b.descend(eps, c, cfg["J_obj"], T, 1, ckpt_every=cfg["ckpt_every"])
+    if warmup:
+        b.descend(eps, c, cfg["J_obj"], T, warmup, ckpt_every=cfg["ckpt_every"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, hist, active = b.descend(eps, c, cfg["J_obj"], T, iters, ckpt_every=cfg["ckpt_every"])
@@ -98,7 +119,10 @@ def adjoint_rate(adscl, T, iters=2):
     n = len(cfg["N"])
     steps = np.ceil(T / (0.25 * (math.pi / 2) / (np.asarray(cfg["N"], np.float64) - 1)) - 1e-9)
     return {"workload": "batched_adjoint_gd_256: 256 instances, N in {2049,4097}, eps log-U[0.02,0.2], 32 modes, "
-                        "J_obj 16, K 512, T=%g (window of the T=100 run), %d descent iterations" % (T, iters),
+                        "J_obj 16, K 512, T=%g%s, %d descent iterations" % (
+                            T, "" if T >= 100 else " (a window of the T=100 run)", iters),
+            "L_first_last_mean_active": [float(np.nanmean(hist[0].cpu().numpy())),
+                                         float(np.nanmean(hist[-1].cpu().numpy()))],
             "grads_per_s": n * iters / dt, "s_per_iteration": dt / iters,
             "forward_pt_steps_per_iteration": float(np.sum(steps * np.asarray(cfg["N"]))),
             "active": int(active.sum().item())}
@@ -274,6 +298,68 @@ def config1_full(adscl, chunk=65536, spectra_out=None):
             "constraints_t0": [float(x) for x in con0], "constraints_end": [float(x) for x in con1]}
 
 
+def qp_sweep(adscl, N, eps_values, t_max, rk, a_reint, chunk=262144):
+    """The paper's collapse-time study (Sec. III): each approximate quasi-periodic
+    family (k_d, mu) of Eq. (13) at every amplitude in `eps_values`, all as one
+    batch on grid N, evolved to t_max or collapse (min A < 0.01, the paper's
+    threshold); per instance the collapse time and the mass loss
+    (M(0) - M(end)) / M(0) of the mass integral of Sec. II, and per family the
+    least-squares line t_c = a + b / eps^2 over the instances that collapsed.
+    Progress goes to stderr, one line per chunk of steps."""
+    import torch
+    from paper_1706_07413_amd import inputs as I
+    fams = I.QP_FAMILIES
+    J = 40
+    rows = [(kd, mu, e) for kd, mu in fams for e in eps_values]
+    n = len(rows)
+    c = np.stack([I.qp_family(kd, mu, J) for kd, mu, _ in rows])
+    eps = np.array([e for _, _, e in rows])
+    b = adscl.Batch([N] * n, a_collapse=0.01, n_modes=J, rk_order=rk, a_reint=a_reint)
+    b.init_modes(eps, np.ascontiguousarray(c))
+    M0 = b.constraints()[:, 4].copy()
+    n_final = int(math.ceil(t_max / (0.25 * (math.pi / 2) / (N - 1)) - 1e-9))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_done = 0
+    while True:
+        b.step(chunk, t_max)
+        st = b.status()
+        running = int(np.sum(st["state"] == adscl.RUNNING))
+        steps_done = int(np.max(st["steps"]))
+        print("qp sweep: step %d of %d, %d running, %d collapsed, %.1f s" % (
+            steps_done, n_final, running, int(np.sum(st["state"] == adscl.COLLAPSED)), time.perf_counter() - t0),
+            file=sys.stderr, flush=True)
+        if running == 0:
+            break
+    elapsed = time.perf_counter() - t0
+    con = b.constraints()
+    b.close()
+    M1 = con[:, 4]
+    work = float(N) * float(np.sum(st["steps"]))
+    fam_out = []
+    for kd, mu in fams:
+        sel = [i for i, r in enumerate(rows) if r[0] == kd and r[1] == mu]
+        tc = [float(st["t_c"][i]) if st["state"][i] == adscl.COLLAPSED else None for i in sel]
+        x = np.array([1.0 / eps[i] ** 2 for i, t in zip(sel, tc) if t is not None])
+        y = np.array([t for t in tc if t is not None])
+        fit = None
+        if len(x) >= 3:
+            B, A0 = np.polyfit(x, y, 1)
+            pred = A0 + B * x
+            r2 = 1.0 - np.sum((y - pred) ** 2) / max(np.sum((y - y.mean()) ** 2), 1e-300)
+            fit = {"intercept": float(A0), "slope": float(B), "r2": float(r2), "points": int(len(x))}
+        fam_out.append({"k_d": kd, "mu": mu, "eps": [float(eps[i]) for i in sel],
+                        "inv_eps2": [float(1.0 / eps[i] ** 2) for i in sel], "t_c": tc,
+                        "state": [int(st["state"][i]) for i in sel],
+                        "mass_loss": [float((M0[i] - M1[i]) / M0[i]) for i in sel],
+                        "max_residual_R_A'": [float(con[i, 0]) for i in sel], "fit_t_c_vs_inv_eps2": fit})
+    return {"workload": "qp_sweep: the four approximate QP families (k_d in {3,5}, mu in {1,1.75}), 40 modes, "
+                        "N=%d, RK%d%s, t_max=%g, collapse at min A < 0.01" % (
+                            N, rk, "" if a_reint == 0 else " with A evolved (re-integrated every %d)" % a_reint,
+                            t_max),
+            "instances": n, "seconds": elapsed, "pt_steps_per_s": work / elapsed, "families": fam_out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +380,21 @@ def main():
                     help="with --config1-full: save the spectra to this .npy file")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint leg and print its result (for profiling it)")
+    ap.add_argument("--adjoint-iters", type=int, default=2, help="timed descent iterations of the adjoint leg")
+    ap.add_argument("--adjoint-warmup", type=int, default=1, help="untimed descent iterations before them")
+    ap.add_argument("--adjoint-full", action="store_true",
+                    help="run only the adjoint workloads at their stated length (T = 100): one gradient of the "
+                         "single instance, then --adjoint-iters descent iterations of the 256 instances")
+    ap.add_argument("--qp-sweep", action="store_true",
+                    help="run only the collapse-time sweep of the approximate quasi-periodic families")
+    ap.add_argument("--qp-n", type=int, default=4097, help="grid of the sweep")
+    ap.add_argument("--qp-eps", default="0.04,0.03525,0.03106,0.02737,0.02412,0.02125,0.01873,0.0165,0.01454,"
+                                        "0.01281,0.01129,0.009951,0.008769,0.007727,0.006809,0.006",
+                    help="comma-separated amplitudes of the sweep")
+    ap.add_argument("--qp-tmax", type=float, default=500.0)
+    ap.add_argument("--qp-rk", type=int, default=3, help="Runge-Kutta order of the sweep (the paper's: 3)")
+    ap.add_argument("--qp-reint", type=int, default=0,
+                    help="0: A solved at every stage; K: A evolved, re-integrated every K steps")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the workload, run a plain device copy of this many bytes "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -324,7 +425,18 @@ def main():
     # measured on this GPU before any timed work
     tuned = adscl.autotune(sorted(set(int(n) for n in cfg["N"]) | {2049, 4097}), steps=256, apply=True)
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_rate(adscl, args.adjoint_t)}))
+        print(json.dumps({"adjoint": adjoint_rate(adscl, args.adjoint_t, args.adjoint_iters, args.adjoint_warmup)}))
+        return
+    if args.adjoint_full:
+        r3 = adjoint_config3(adscl)
+        print("adjoint_N4097 T=100: %.1f s per gradient" % r3["s_per_gradient"], file=sys.stderr, flush=True)
+        r4 = adjoint_rate(adscl, 100.0, args.adjoint_iters, 0)
+        print(json.dumps({"adjoint_config3_T100": r3, "adjoint_gd256_T100": r4}))
+        return
+    if args.qp_sweep:
+        eps_values = [float(e) for e in args.qp_eps.split(",")]
+        print(json.dumps({"qp_sweep": qp_sweep(adscl, args.qp_n, eps_values, args.qp_tmax, args.qp_rk,
+                                               args.qp_reint)}))
         return
     if args.config1_full:
         print(json.dumps({"config1_full": config1_full(adscl, spectra_out=args.spectra_out)}))
@@ -420,7 +532,7 @@ def main():
         out["large_instance"] = large_instance_rate(adscl)
         out["paper_tables"] = paper_table_rates(adscl)
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_rate(adscl, args.adjoint_t)
+        out["adjoint"] = adjoint_rate(adscl, args.adjoint_t, args.adjoint_iters, args.adjoint_warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_instances, args.cpu_steps)
     batch.close()

@@ -76,4 +76,18 @@ def config4(B=256):
                 T=100.0, J_obj=16, ckpt_every=512, gd_iters=50, gauge=GAUGE_BOUNDARY, a_collapse=0.01)
 
 
+def qp_family(kd, mu, J=40):
+    """Mode-sum coefficients of the paper's approximate quasi-periodic families
+    (Sec. II, Eq. (13)): amplitudes A_k = eps exp(-mu |k - k_d|) of phi in mode
+    k, i.e. Pi(x,0) = eps sum_{k<J} omega_k exp(-mu |k - k_d|) e_k(x) with
+    omega_k = 3 + 2k, Phi(x,0) = 0.  Returns the J coefficients of e_k (eps
+    applied separately, as adscl_init_modes takes it)."""
+    k = np.arange(J)
+    return (3.0 + 2.0 * k) * np.exp(-mu * np.abs(k - kd))
+
+
+# the four families the paper evolves: (k_d, mu)
+QP_FAMILIES = ((3, 1.0), (3, 1.75), (5, 1.0), (5, 1.75))
+
+
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
