@@ -395,13 +395,15 @@ struct Rev {
             }
         }
 
-        // stage values, re-read from the scratch where they are used
-        double Eb[P], Sb[P];
+        // stage values: e^-delta held through the reverse scans, Phi_s, Pi_s re-read
+        double Eb[P], Sb[P], VE[P];
         {
             const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
+            for (int k = 0; k < P; ++k) VE[k] = sv.ld(f0 + 2, k);
+#pragma unroll
             for (int k = 0; k < P; ++k) {
-                const double v0 = sv.ld(f0, k), v1 = sv.ld(f0 + 1, k), E = sv.ld(f0 + 2, k), S = sv.ld(f0 + 3, k);
+                const double v0 = sv.ld(f0, k), v1 = sv.ld(f0 + 1, k), E = VE[k], S = sv.ld(f0 + 3, k);
             double f2b = sg.tab(tb, 1, k) * gb[k];
             if (tid == 0 && k == 1) f2b += 16.0 * ob;
             if (tid == 0 && k == 2) f2b -= 2.0 * ob;
@@ -416,7 +418,8 @@ struct Rev {
             }
         }
         constraint_reverse(
-            sg, [&](int f, int k) -> double { return lane_arr<P, NL>(stg, tid).ld(f0 + f, k); }, Eb, Sb, vb0, vb1);
+            sg, [&](int f, int k) -> double { return f == 2 ? VE[k] : lane_arr<P, NL>(stg, tid).ld(f0 + f, k); }, Eb,
+            Sb, vb0, vb1);
         if (tid == 0) vb0[0] = 0.0;  // Phi_0 is pinned
     }
 };
