@@ -9,7 +9,8 @@
   The instances were picked with the oracle alone: the earliest collapse time
   of each grid size among the draw (a proxy run of every instance at
   N = 1025, then the true grid), and the N = 1025 instance of smallest
-  eps sigma^(3/2).
+  eps sigma^(3/2), whose state is also compared every 10 430 steps (the
+  error against step count over the whole run).
 * The single-instance adjoint workload at its stated size (N = 4097, T = 100,
   1 043 038 steps, 32 mode coefficients, drift of 16 mode energies, checkpoints
   every 512 steps): the gradient against central differences h = 1e-6 of the
@@ -29,6 +30,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 TOL = 1e-11
 FIELDS = ("Phi", "Pi", "A", "delta", "m")
+# the instance run to t = 50, and its stored states (every 10 430 steps = 4 time units)
+LONG, EVERY, SLOTS = 409, 10430, 13
 # instance index in the draw -> expected oracle outcome (documentation; the
 # test recomputes it)
 PICKS = {949: "collapses at step 2744 (N = 1025)", 364: "collapses at step 5008 (N = 2049)",
@@ -49,6 +52,9 @@ def test_benchmark_workload_whole_run_sampled_instances_match_oracle():
     def oracle_run(i):
         Phi, Pi = O.init_gaussian(int(c["N"][i]), c["eps"][i], c["sigma"][i])
         n_final = O.n_steps_for(c["T"], int(c["N"][i]))
+        if i == LONG:
+            return O.evolve(Phi, Pi, n_final, gauge=c["gauge"], a_collapse=c["a_collapse"], snap_every=EVERY,
+                            n_slots=SLOTS)
         return O.evolve(Phi, Pi, n_final, gauge=c["gauge"], a_collapse=c["a_collapse"])
 
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(picks)) as ex:
@@ -62,9 +68,24 @@ def test_benchmark_workload_whole_run_sampled_instances_match_oracle():
             s = b.status()
             st = {k: v.cpu().numpy() for k, v in b.get_state().items()}
             b.close()
+            # the 130 380-step instance alone, with its state every EVERY steps
+            import torch
+            one = adscl.Batch(c["N"][LONG:LONG + 1], gauge=c["gauge"], a_collapse=c["a_collapse"])
+            one.init_gaussian(c["eps"][LONG:LONG + 1], c["sigma"][LONG:LONG + 1])
+            snaps = torch.zeros((SLOTS, 5, one.total), dtype=torch.float64, device="cuda")
+            one.step(1 << 40, c["T"], snap_every=EVERY, snaps=snaps)
+            sn = snaps.cpu().numpy()
+            one.close()
         finally:
             adscl.autotune_clear()
         refs = {i: f.result() for i, f in futs.items()}
+    # error against step count over the long run (the bar holds at every stored state)
+    growth = []
+    for sl in range(SLOTS):
+        growth.append(max(rel(sn[sl, f], refs[LONG]["snaps"][sl, f]) for f in range(5)))
+    print("error of the N = 1025 run against step count:",
+          ", ".join("%d: %.1e" % (sl * EVERY, e) for sl, e in enumerate(growth)))
+    assert all(e <= TOL for e in growth), growth
     errs = {}
     for i in picks:
         r = refs[i]
