@@ -43,6 +43,15 @@ struct LaunchClass {
     int* err = nullptr;
 };
 
+// One cooperative launch of the multi-workgroup kernel over several large
+// instances (classes `cls` of the context, all in configuration cfg).
+struct BigGroup {
+    ClassCfg cfg;
+    int blocks = 0;
+    std::vector<int> cls;
+    BigDesc* d_desc = nullptr;
+};
+
 // Host-side tables of one grid size N.
 struct NTables {
     ClassCfg cfg;
@@ -84,6 +93,7 @@ struct adscl_ctx {
     std::map<std::string, std::pair<void*, size_t>> bufs;
     hipEvent_t fork = nullptr;  // start of a multi-class launch, recorded on `stream`
     int n_big = 0;              // classes holding one large (multi-workgroup) instance
+    std::vector<BigGroup> big_groups;  // their launches
     // spectrum rows for states laid out as [slot][5][total], grouped by N:
     // (N, first row, rows) per group, for spec_slots slots
     int spec_slots = -1;
@@ -376,21 +386,22 @@ EvolveArgs evolve_args(adscl_ctx* c, int32_t snap_every)
 // its target step, or to its next multiple of snap_every when that is > 0.
 int run_evolve(adscl_ctx* c, const EvolveArgs& base, bool timing = true)
 {
-    for (LaunchClass& lc : c->classes) {
-        if (lc.chunks == 0) continue;
+    for (BigGroup& g : c->big_groups) {
         BigArgs x;
-        x.inst = lc.inst[0];
-        x.chunks = lc.chunks;
-        x.xch = lc.xch;
-        x.ctr = lc.ctr;
-        x.err = lc.err;
+        x.desc = g.d_desc;
+        x.n_desc = (int32_t)g.cls.size();
+        x.pad = 0;
         EvolveArgs a = base;
         a.order = nullptr;
-        if (timing && lc.t0) HIP_TRY(c, hipEventRecord(lc.t0, c->stream));
-        HIP_TRY(c, launch_evolve_big(lc.cfg, lc.chunks, a, x, c->stream));
-        if (timing && lc.t1) {
-            HIP_TRY(c, hipEventRecord(lc.t1, c->stream));
-            lc.timed = true;
+        for (int k : g.cls)
+            if (timing && c->classes[k].t0) HIP_TRY(c, hipEventRecord(c->classes[k].t0, c->stream));
+        HIP_TRY(c, launch_evolve_big(g.cfg, g.blocks, a, x, c->stream));
+        for (int k : g.cls) {
+            LaunchClass& lc = c->classes[k];
+            if (timing && lc.t1) {
+                HIP_TRY(c, hipEventRecord(lc.t1, c->stream));
+                lc.timed = true;
+            }
         }
     }
     return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
@@ -995,14 +1006,58 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     if (c->classes.size() > 1) TRY_C(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
     // one-workgroup classes by lane capacity, largest first (their launch
     // order); large instances are listed last, but run_evolve launches them
-    // first, one after another on the context stream, before it forks the
-    // one-workgroup classes onto their streams: the two never overlap
+    // first, all in one cooperative launch per chunk configuration on the
+    // context stream (several when the device cannot hold their workgroups
+    // at once), before it forks the one-workgroup classes onto their streams:
+    // the two never overlap
     std::stable_sort(c->classes.begin(), c->classes.end(), [](const LaunchClass& x, const LaunchClass& y) {
         if ((x.chunks > 0) != (y.chunks > 0)) return y.chunks > 0;
         return 64 * x.cfg.W * x.cfg.P > 64 * y.cfg.W * y.cfg.P;
     });
     c->n_big = 0;
     for (const LaunchClass& lc : c->classes) c->n_big += lc.chunks > 0;
+    // large instances: one cooperative launch per configuration, split where
+    // the device cannot hold all their workgroups at once
+    for (int k = 0; k < (int)c->classes.size(); ++k) {
+        const LaunchClass& lc = c->classes[k];
+        if (lc.chunks == 0) continue;
+        int cap = 0;
+        TRY_C(big_capacity(lc.cfg, c->device, &cap));
+        if (lc.chunks > cap) {
+            c->err = "N=" + std::to_string(c->N[lc.inst[0]]) + " needs " + std::to_string(lc.chunks) +
+                     " workgroups at once, the device holds " + std::to_string(cap);
+            return bail(ADSCL_EUNSUPPORTED);
+        }
+        BigGroup* g = nullptr;
+        for (BigGroup& x : c->big_groups)
+            if (x.cfg.P == lc.cfg.P && x.cfg.W == lc.cfg.W && x.blocks + lc.chunks <= cap && x.cls.size() < 1024)
+                g = &x;
+        if (!g) {
+            c->big_groups.emplace_back();
+            g = &c->big_groups.back();
+            g->cfg = lc.cfg;
+        }
+        g->cls.push_back(k);
+        g->blocks += lc.chunks;
+    }
+    for (BigGroup& g : c->big_groups) {
+        std::vector<BigDesc> desc;
+        int first = 0;
+        for (int k : g.cls) {
+            const LaunchClass& lc = c->classes[k];
+            BigDesc d;
+            d.inst = lc.inst[0];
+            d.chunks = lc.chunks;
+            d.first = first;
+            d.pad = 0;
+            d.xch = lc.xch;
+            d.ctr = lc.ctr;
+            desc.push_back(d);
+            first += lc.chunks;
+        }
+        TRY_C(hipMalloc((void**)&g.d_desc, sizeof(BigDesc) * desc.size()));
+        TRY_C(hipMemcpy(g.d_desc, desc.data(), sizeof(BigDesc) * desc.size(), hipMemcpyHostToDevice));
+    }
 
     std::vector<const double*> tabp(c->n_inst), ep(c->n_inst), wpp(c->n_inst), wfp(c->n_inst);
     for (int b = 0; b < c->n_inst; ++b) {
@@ -1039,6 +1094,8 @@ void adscl_destroy(adscl_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (BigGroup& g : c->big_groups)
+        if (g.d_desc) (void)hipFree(g.d_desc);
     for (LaunchClass& lc : c->classes) {
         if (lc.xch) (void)hipFree(lc.xch);
         if (lc.ctr) (void)hipFree(lc.ctr);

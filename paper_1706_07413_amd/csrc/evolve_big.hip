@@ -20,6 +20,12 @@
 //      D_g = sum_{h<g} F_h (sigma' total of h);
 //   C  fluxes: each chunk's first and last two (f1, g) values, and the
 //      collapse / non-finite bits of the step's first stage.
+// Several large instances share one cooperative launch (as many as the device
+// holds at once): each workgroup finds its instance in the launch's table of
+// instances and its chunk within it, and every instance keeps its own records
+// and counter, so the instances run side by side and only wait for their own
+// chunks.
+//
 // The synchronisation is a monotonic 64-bit arrival counter per instance:
 // every workgroup adds one and waits, with a bounded spin, until all G have
 // arrived; a spin that runs out sets an error flag and every workgroup leaves
@@ -474,7 +480,11 @@ template <int P, int W>
 __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArgs x)
 {
     extern __shared__ double lds[];
-    const int b = x.inst;
+    // this workgroup's instance in the launch (workgroup-uniform)
+    int d = 0;
+    while (d + 1 < x.n_desc && (int)blockIdx.x >= x.desc[d + 1].first) ++d;
+    const BigDesc bd = x.desc[d];
+    const int b = bd.inst;
     const InstStatus st0 = a.status[b];
     if (st0.state == ST_COLLAPSED || st0.state == ST_NONFINITE) return;
     const InstConst ic = a.ic[b];
@@ -488,8 +498,8 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.tid = threadIdx.x;
     cs.lane = cs.tid & 63;
     cs.wv = cs.tid >> 6;
-    cs.g = blockIdx.x;
-    cs.G = x.chunks;
+    cs.g = (int)blockIdx.x - bd.first;
+    cs.G = bd.chunks;
     cs.a = cs.g * Ch::C;
     cs.i0 = cs.a + cs.tid * P;
     cs.col = cs.tid + 1;
@@ -511,9 +521,9 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.T = cs.red + 4 * W + 8 + 3 * 64;
 #pragma unroll
     for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
-    cs.xg = x.xch;
-    cs.ctr = x.ctr;
-    cs.err = x.err;
+    cs.xg = bd.xch;
+    cs.ctr = bd.ctr;
+    cs.err = reinterpret_cast<int*>(bd.ctr + 1);
     cs.target = 0;
     const double dt = ic.dt;
     const int i0 = cs.i0;
@@ -600,25 +610,41 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     }
 }
 
-__global__ void big_reset_kernel(unsigned long long* ctr, int* err)
+// Counters and error flags of the launch's instances to zero.
+__global__ void big_reset_kernel(BigArgs x)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *ctr = 0ull;
-        *err = 0;
+    const int d = threadIdx.x;
+    if (d < x.n_desc) {
+        x.desc[d].ctr[0] = 0ull;
+        x.desc[d].ctr[1] = 0ull;
     }
 }
 
 template <int P, int W>
-hipError_t launch_big_t(int chunks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
+hipError_t launch_big_t(int blocks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
 {
-    big_reset_kernel<<<dim3(1), dim3(64), 0, s>>>(x.ctr, x.err);
+    if (x.n_desc < 1 || x.n_desc > 1024) return hipErrorInvalidValue;
+    big_reset_kernel<<<dim3(1), dim3(1024), 0, s>>>(x);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = big_lds_bytes_for<P, W>();
     EvolveArgs ea = a;
     BigArgs xa = x;
     void* args[] = {(void*)&ea, (void*)&xa};
-    return hipLaunchCooperativeKernel((const void*)evolve_big_kernel<P, W>, dim3(chunks), dim3(64 * W), args, lds, s);
+    return hipLaunchCooperativeKernel((const void*)evolve_big_kernel<P, W>, dim3(blocks), dim3(64 * W), args, lds, s);
+}
+
+template <int P, int W>
+hipError_t capacity_t(int device, int* blocks)
+{
+    int cus = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)evolve_big_kernel<P, W>, 64 * W,
+                                                     big_lds_bytes_for<P, W>());
+    if (e != hipSuccess) return e;
+    *blocks = per_cu * cus;
+    return hipSuccess;
 }
 
 template <int P, int W>
@@ -660,10 +686,19 @@ hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_evolve_big(ClassCfg c, int chunks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
+hipError_t launch_evolve_big(ClassCfg c, int blocks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
 {
 #define X(p, w) \
-    if (c.P == p && c.W == w) return launch_big_t<p, w>(chunks, a, x, s);
+    if (c.P == p && c.W == w) return launch_big_t<p, w>(blocks, a, x, s);
+    ADSCL_BIG_CLASSES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t big_capacity(ClassCfg c, int device, int* blocks)
+{
+#define X(p, w) \
+    if (c.P == p && c.W == w) return capacity_t<p, w>(device, blocks);
     ADSCL_BIG_CLASSES(X)
 #undef X
     return hipErrorInvalidValue;

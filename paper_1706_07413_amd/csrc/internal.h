@@ -87,17 +87,29 @@ hipError_t launch_evolve_scheme(ClassCfg c, int rk, bool eva, bool full, int n_b
 // One large instance over `chunks` workgroups of a (P, W) chunk class
 // (cooperative launch): its index, the exchange records [chunks][32], and an
 // arrival counter and error flag of its own.
+// One large instance of a (merged) launch of the multi-workgroup kernel: its
+// workgroups are [first, first + chunks) of the launch.
+struct BigDesc {
+    int32_t inst;             // instance index
+    int32_t chunks;           // G
+    int32_t first;            // its first workgroup in the launch
+    int32_t pad;
+    double* xch;              // exchange records [G][32]
+    unsigned long long* ctr;  // arrival counter, then the error flag (int)
+};
 struct BigArgs {
-    int32_t inst;
-    int32_t chunks;
-    double* xch;
-    unsigned long long* ctr;
-    int* err;
+    const BigDesc* desc;      // device [n_desc]
+    int32_t n_desc;
+    int32_t pad;
 };
 bool big_class_supported(ClassCfg c);
 size_t big_lds_bytes(ClassCfg c);
 hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds);
-hipError_t launch_evolve_big(ClassCfg c, int chunks, const EvolveArgs& a, const BigArgs& x, hipStream_t s);
+// Workgroups of the multi-workgroup kernel in configuration c the device holds at once.
+hipError_t big_capacity(ClassCfg c, int device, int* blocks);
+// One cooperative launch of `blocks` workgroups over the instances of x (all in
+// configuration c, sum of their chunks = blocks <= big_capacity).
+hipError_t launch_evolve_big(ClassCfg c, int blocks, const EvolveArgs& a, const BigArgs& x, hipStream_t s);
 constexpr int kBigMaxChunks = 96;
 
 // Initial data: Pi = (2 eps/pi) exp(-4 tan^2 x/(pi^2 sigma^2)), Phi = 0 (pins applied).

@@ -6,6 +6,8 @@ every stage.  The computation is the same scheme with the prefix sums
 re-associated (a chunk's carry enters as one factor), so the fields must match
 the oracle to the same 1e-11 relative max-norm as the single-workgroup path.
 """
+import concurrent.futures
+
 import numpy as np
 import pytest
 
@@ -156,3 +158,46 @@ def test_dynamic_metric_on_the_speed_table_grids(N, n):
     ref = O.evolve(Phi, Pi, n)
     for f in FIELDS:
         assert_close(g[f], ref[f], "N=%d %s" % (N, f))
+
+
+def test_several_large_instances_side_by_side():
+    """Five large instances (three grid sizes, one collapsing early at the
+    oracle's step) share one cooperative launch next to a small one: each
+    matches the oracle, and each is bitwise equal to itself run alone."""
+    Ns = np.array([8193, 4609, 6145, 257, 8193, 10001], np.int32)
+    eps = np.array([5.0, 60.0, 4.0, 2.0, 3.0, 6.0])
+    sig = np.array([0.2, 0.08, 0.25, 0.2, 0.3, 0.2])
+    thr = 0.2
+    n = 1500
+    print("several large", flush=True)
+    O.grid(17)  # load the oracle before its worker threads call it
+
+    def oracle_run(i):
+        Phi, Pi = O.init_gaussian(int(Ns[i]), float(eps[i]), float(sig[i]))
+        return O.evolve(Phi, Pi, n, a_collapse=thr)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(Ns)) as ex:
+        futs = [ex.submit(oracle_run, i) for i in range(len(Ns))]
+        b = adscl.Batch(Ns, a_collapse=thr)
+        b.init_gaussian(eps, sig)
+        b.step(n, 1e9)
+        st = b.status()
+        g = gpu_state(b)
+        b.close()
+        refs = [f.result() for f in futs]
+    for i, N in enumerate(Ns):
+        ref = refs[i]
+        assert st["steps"][i] == ref["steps"], (i, st["steps"][i], ref["steps"])
+        want = adscl.RUNNING if ref["state"] == O.DONE else ref["state"]
+        assert st["state"][i] == want, i
+        for f in FIELDS:
+            assert_close(b.split(g[f])[i], ref[f], "N=%d #%d %s" % (N, i, f))
+    assert st["state"][1] == adscl.COLLAPSED and st["steps"][1] < n
+    for i in (0, 5):
+        one = adscl.Batch(Ns[i:i + 1], a_collapse=thr)
+        one.init_gaussian(eps[i:i + 1], sig[i:i + 1])
+        one.step(n, 1e9)
+        g1 = gpu_state(one)
+        one.close()
+        for f in FIELDS:
+            assert np.array_equal(b.split(g[f])[i], g1[f]), (i, f)
