@@ -44,16 +44,28 @@ PEAK_HBM_GBS = 8000.0
 # the sources in this tree: after any change to the kernel they are null until
 # measured again.
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "evolve_batched1024_counters.md")
-KERNEL_SOURCES = ["paper_1706_07413_amd/csrc/stage.h", "paper_1706_07413_amd/csrc/evolve.hip",
-                  "paper_1706_07413_amd/csrc/internal.h", "paper_1706_07413_amd/build.py"]
 
 
 def kernel_digest():
+    """Digest of what the forward kernel is compiled from: stage.h and
+    evolve.hip whole, the declarations of internal.h it uses (the per-instance
+    status and constants and the kernel's argument block) and its compiler
+    flags in build.py."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1706_07413_amd", "csrc")
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in ("stage.h", "evolve.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "internal.h")) as fh:
+        t = fh.read()
+    i = t.index("struct InstStatus")
+    j = t.index("};", t.index("struct EvolveArgs")) + 2
+    h.update(t[i:j].encode())
+    with open(os.path.join(ROOT, "paper_1706_07413_amd", "build.py")) as fh:
+        t = fh.read()
+    h.update(t[t.index("def common_flags"):t.index("def _compile")].encode())
+    h.update([l for l in t.splitlines() if l.startswith('EXTRA = {"evolve.hip"')][0].encode())
     return h.hexdigest()[:16]
 
 

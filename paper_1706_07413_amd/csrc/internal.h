@@ -84,9 +84,6 @@ hipError_t prepare_evolve_scheme(ClassCfg c, int rk, bool eva, size_t max_lds);
 hipError_t launch_evolve_scheme(ClassCfg c, int rk, bool eva, bool full, int n_blocks, const EvolveArgs& a,
                                 hipStream_t s);
 
-// One large instance over `chunks` workgroups of a (P, W) chunk class
-// (cooperative launch): its index, the exchange records [chunks][32], and an
-// arrival counter and error flag of its own.
 // One large instance of a (merged) launch of the multi-workgroup kernel: its
 // workgroups are [first, first + chunks) of the launch.
 struct BigDesc {
