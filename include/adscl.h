@@ -85,8 +85,8 @@ typedef struct {
      *   every stage), and replaces it by Eq. (5)'s solution at the start of every
      *   step that is a multiple of K; collapse is then tested on the evolved A,
      *   which adscl_get_state returns (delta and m come from the constraints).
-     * Other than (4, 0): EINVAL with ADSCL_FROZEN_METRIC and a_reint > 0,
-     * EUNSUPPORTED for N_b > 4097 and for adscl_adjoint / adscl_descend. */
+     * EINVAL with ADSCL_FROZEN_METRIC and a_reint > 0; other than (4, 0):
+     * EUNSUPPORTED for adscl_adjoint / adscl_descend. */
     int32_t rk_order;
     int32_t a_reint;
 } adscl_config;

@@ -38,9 +38,6 @@ struct LaunchClass {
     bool timed = false;
     // one large instance over `chunks` workgroups (0: one workgroup per instance)
     int chunks = 0;
-    double* xch = nullptr;              // exchange records [chunks][32]
-    unsigned long long* ctr = nullptr;  // arrival counter, then the error flag
-    int* err = nullptr;
 };
 
 // One cooperative launch of the multi-workgroup kernel over several large
@@ -50,6 +47,8 @@ struct BigGroup {
     int blocks = 0;
     std::vector<int> cls;
     BigDesc* d_desc = nullptr;
+    double* xch = nullptr;              // exchange records [blocks][32]
+    unsigned long long* ctr = nullptr;  // [cls.size()][2]: arrival counter, error flag
 };
 
 // Host-side tables of one grid size N.
@@ -389,13 +388,15 @@ int run_evolve(adscl_ctx* c, const EvolveArgs& base, bool timing = true)
     for (BigGroup& g : c->big_groups) {
         BigArgs x;
         x.desc = g.d_desc;
+        x.xch = g.xch;
+        x.ctr = g.ctr;
         x.n_desc = (int32_t)g.cls.size();
         x.pad = 0;
         EvolveArgs a = base;
         a.order = nullptr;
         for (int k : g.cls)
             if (timing && c->classes[k].t0) HIP_TRY(c, hipEventRecord(c->classes[k].t0, c->stream));
-        HIP_TRY(c, launch_evolve_big(g.cfg, g.blocks, a, x, c->stream));
+        HIP_TRY(c, launch_evolve_big(g.cfg, c->rk, c->a_reint > 0, g.blocks, a, x, c->stream));
         for (int k : g.cls) {
             LaunchClass& lc = c->classes[k];
             if (timing && lc.t1) {
@@ -502,14 +503,18 @@ int run_call(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every, 
 // an error; its state is then NONFINITE).  Synchronises.
 int check_big(adscl_ctx* c)
 {
-    for (const LaunchClass& lc : c->classes) {
-        if (lc.chunks == 0) continue;
-        int e = 0;
-        HIP_TRY(c, hipMemcpyAsync(&e, lc.err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    for (const BigGroup& g : c->big_groups) {
+        std::vector<unsigned long long> ctr(2 * g.cls.size());
+        HIP_TRY(c, hipMemcpyAsync(ctr.data(), g.ctr, sizeof(unsigned long long) * ctr.size(), hipMemcpyDeviceToHost,
+                                  c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (e)
-            return fail(c, ADSCL_EHIP, "instance " + std::to_string(lc.inst[0]) +
-                                           ": a grid synchronisation of its workgroups timed out");
+        for (size_t d = 0; d < g.cls.size(); ++d) {
+            int e = 0;
+            std::memcpy(&e, &ctr[2 * d + 1], sizeof(int));
+            if (e)
+                return fail(c, ADSCL_EHIP, "instance " + std::to_string(c->classes[g.cls[d]].inst[0]) +
+                                               ": a grid synchronisation of its workgroups timed out");
+        }
     }
     return ADSCL_OK;
 }
@@ -824,11 +829,6 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     if (cfg->a_reint > 0 && (cfg->flags & ADSCL_FROZEN_METRIC))
         return fail(nullptr, ADSCL_EINVAL, "an evolved A (a_reint > 0) needs the dynamic metric");
     const int rk_order = cfg->rk_order == 0 ? 4 : cfg->rk_order;
-    if (rk_order != 4 || cfg->a_reint > 0)
-        for (int b = 0; b < cfg->n_inst; ++b)
-            if (cfg->n_grid[b] > kMaxOneGroup)
-                return fail(nullptr, ADSCL_EUNSUPPORTED,
-                            "the scheme options (rk_order != 4 or a_reint > 0) support N <= 4097");
 
     adscl_ctx* c = new adscl_ctx();
     c->n_inst = cfg->n_inst;
@@ -917,7 +917,7 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
             if (!c->tables.count(N)) {
                 NTables t;
                 t.cfg = cfg;
-                TRY_C(prepare_evolve_big(cfg, c->max_lds));
+                TRY_C(prepare_evolve_big(cfg, c->rk, c->a_reint > 0, c->max_lds));
                 std::vector<double> tab, e, wpi, wphi;
                 host_tables(N, cfg, tab, G);
                 TRY_C(hipMalloc((void**)&t.d_tab, tab.size() * sizeof(double)));
@@ -939,10 +939,6 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
             lc.full = false;
             lc.chunks = G;
             lc.inst.push_back(b);
-            TRY_C(hipMalloc((void**)&lc.xch, sizeof(double) * 32 * (size_t)G));
-            TRY_C(hipMalloc((void**)&lc.ctr, sizeof(unsigned long long) * 2));
-            lc.err = (int*)(lc.ctr + 1);
-            TRY_C(hipMemset(lc.ctr, 0, sizeof(unsigned long long) * 2));
             c->classes.push_back(lc);
             continue;
         }
@@ -1022,7 +1018,7 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
         const LaunchClass& lc = c->classes[k];
         if (lc.chunks == 0) continue;
         int cap = 0;
-        TRY_C(big_capacity(lc.cfg, c->device, &cap));
+        TRY_C(big_capacity(lc.cfg, c->rk, c->a_reint > 0, c->device, &cap));
         if (lc.chunks > cap) {
             c->err = "N=" + std::to_string(c->N[lc.inst[0]]) + " needs " + std::to_string(lc.chunks) +
                      " workgroups at once, the device holds " + std::to_string(cap);
@@ -1050,13 +1046,14 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
             d.chunks = lc.chunks;
             d.first = first;
             d.pad = 0;
-            d.xch = lc.xch;
-            d.ctr = lc.ctr;
             desc.push_back(d);
             first += lc.chunks;
         }
         TRY_C(hipMalloc((void**)&g.d_desc, sizeof(BigDesc) * desc.size()));
         TRY_C(hipMemcpy(g.d_desc, desc.data(), sizeof(BigDesc) * desc.size(), hipMemcpyHostToDevice));
+        TRY_C(hipMalloc((void**)&g.xch, sizeof(double) * 32 * (size_t)g.blocks));
+        TRY_C(hipMalloc((void**)&g.ctr, sizeof(unsigned long long) * 2 * desc.size()));
+        TRY_C(hipMemset(g.ctr, 0, sizeof(unsigned long long) * 2 * desc.size()));
     }
 
     std::vector<const double*> tabp(c->n_inst), ep(c->n_inst), wpp(c->n_inst), wfp(c->n_inst);
@@ -1094,11 +1091,12 @@ void adscl_destroy(adscl_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (BigGroup& g : c->big_groups)
+    for (BigGroup& g : c->big_groups) {
         if (g.d_desc) (void)hipFree(g.d_desc);
+        if (g.xch) (void)hipFree(g.xch);
+        if (g.ctr) (void)hipFree(g.ctr);
+    }
     for (LaunchClass& lc : c->classes) {
-        if (lc.xch) (void)hipFree(lc.xch);
-        if (lc.ctr) (void)hipFree(lc.ctr);
         if (lc.d_order) (void)hipFree(lc.d_order);
         if (lc.stream) (void)hipStreamDestroy(lc.stream);
         if (lc.done) (void)hipEventDestroy(lc.done);

@@ -200,9 +200,16 @@ struct Chunk {
     // Right-hand sides at the published stage input (after exchange_u).  With
     // `check`, the collapse / non-finite bits of the whole instance are
     // returned (nothing else is computed when any is set).  Returns -1 when a
-    // grid synchronisation failed.
-    __device__ __forceinline__ int rhs(bool check, double* r0, double* r1)
+    // grid synchronisation failed.  EVA (A evolved by Eq. (4)): the stage's A
+    // of the own points is `av`; only delta's prefix sum runs, the fluxes take
+    // w = av e^-delta and the collapse test is av < thr; with `reint` the full
+    // solve runs and its A, 1 - cos^3 x/sin x S/e^-delta, replaces `av`.
+    // `wout` receives w = A e^-delta of the own points (EVA).
+    template <bool EVA = false>
+    __device__ __forceinline__ int rhs(bool check, double* r0, double* r1, double* av = nullptr,
+                                       double* wout = nullptr, bool reint = false)
     {
+        const bool solveS = !EVA || reint;
         __syncthreads();  // B0
         const auto tb = tables();
         double ko0[P], ko1[P], q[P];
@@ -287,20 +294,23 @@ struct Chunk {
                 const double pp = (k == P - 1) ? pr : p[k + 1];
                 dp[k] = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp);
                 E[k] = exp(-dp[k]);
-                sg[k] = tab(tb, 1, k) * q[k] * E[k];
+                sg[k] = solveS ? tab(tb, 1, k) * q[k] * E[k] : 0.0;
                 stot += sg[k];
             }
-            const double incl2 = wave_incl_scan(stot);
-            if (lane == 63) red[W + wv] = incl2;
-            SE[tid] = sg[0];
-            SE[NL + tid] = sg[P - 1];
-            __syncthreads();  // B2
-            double carry2 = incl2 - stot, tot2 = 0.0;
+            double carry2 = 0.0, tot2 = 0.0;
+            if (solveS) {  // uniform: the sigma' prefix sums only where S is needed
+                const double incl2 = wave_incl_scan(stot);
+                if (lane == 63) red[W + wv] = incl2;
+                SE[tid] = sg[0];
+                SE[NL + tid] = sg[P - 1];
+                __syncthreads();  // B2
+                carry2 = incl2 - stot;
 #pragma unroll
-            for (int v = 0; v < W; ++v) {
-                const double t = red[W + v];
-                if (v < wv) carry2 += t;
-                tot2 += t;
+                for (int v = 0; v < W; ++v) {
+                    const double t = red[W + v];
+                    if (v < wv) carry2 += t;
+                    tot2 += t;
+                }
             }
             // sync B: chunk totals and edge values
             if (tid == 0) {
@@ -335,9 +345,10 @@ struct Chunk {
             const double Fg = fac[g];
             double Dg = 0.0;
             for (int c = 0; c < g; ++c) Dg += fac[G + c];
-            const double sl = (tid > 0) ? SE[NL + tid - 1]
+            const double sl = !solveS ? 0.0 : (tid > 0) ? SE[NL + tid - 1]
                                         : (first ? sg[1] : rec(g - 1)[XS_SL] * fac[g - 1] / Fg);
-            const double sr = (tid < NL - 1) ? SE[tid + 1] : (last ? 0.0 : rec(g + 1)[XS_SF] * fac[g + 1] / Fg);
+            const double sr = !solveS ? 0.0 : (tid < NL - 1) ? SE[tid + 1]
+                                        : (last ? 0.0 : rec(g + 1)[XS_SF] * fac[g + 1] / Fg);
             {
                 double R2 = carry2;
 #pragma unroll
@@ -363,7 +374,14 @@ struct Chunk {
             if (own(k)) {
                 const double2 v = U[k * RS + col];
                 const double c3s = tab(tb, 2, k) * tab(tb, 0, k);
-                const double wk = E[k] - c3s * S[k];
+                double wk;
+                if constexpr (EVA) {
+                    if (reint) av[k] = 1.0 - c3s * (S[k] / E[k]);
+                    wk = av[k] * E[k];
+                    wout[k] = wk;
+                } else {
+                    wk = E[k] - c3s * S[k];
+                }
                 const double f1 = wk * v.y;
                 const double f2 = wk * v.x;
                 const double gk = tab(tb, 1, k) * f2;
@@ -476,7 +494,11 @@ constexpr size_t big_lds_bytes_for()
     return (StageLayout<P, W>::lds_doubles + (size_t)3 * 64 + (size_t)3 * P * 64 * W) * sizeof(double);
 }
 
-template <int P, int W>
+// RK: Runge-Kutta order (4 classical; 3 and 2 the Shu-Osher methods, as the
+// one-workgroup scheme kernel); EVA: A evolved by Eq. (4) and re-integrated
+// from Eq. (5) at steps that are multiples of a.a_reint (its A row of the
+// packed state holds the evolved A between calls).
+template <int P, int W, int RK, bool EVA>
 __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArgs x)
 {
     extern __shared__ double lds[];
@@ -521,21 +543,26 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.T = cs.red + 4 * W + 8 + 3 * 64;
 #pragma unroll
     for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
-    cs.xg = bd.xch;
-    cs.ctr = bd.ctr;
-    cs.err = reinterpret_cast<int*>(bd.ctr + 1);
+    cs.xg = x.xch + (size_t)bd.first * XREC;
+    cs.ctr = x.ctr + 2 * d;
+    cs.err = reinterpret_cast<int*>(x.ctr + 2 * d + 1);
     cs.target = 0;
     const double dt = ic.dt;
     const int i0 = cs.i0;
 
-    double un0[P], un1[P], acc0[P], acc1[P];
+    const int64_t K = a.a_reint;
+    // u: U^n; cv: the current stage input; acc: the RK4 accumulator
+    double un0[P], un1[P], unA[P], cv0[P], cv1[P], cvA[P], acc0[P], acc1[P], accA[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const bool o = cs.own(k);
         un0[k] = o ? a.Phi[ic.off + i0 + k] : 0.0;
         un1[k] = o ? a.Pi[ic.off + i0 + k] : 0.0;
-        acc0[k] = 0.0;
-        acc1[k] = 0.0;
+        unA[k] = (EVA && o) ? a.A[ic.off + i0 + k] : 1.0;
+        cv0[k] = un0[k];
+        cv1[k] = un1[k];
+        cvA[k] = unA[k];
+        acc0[k] = acc1[k] = accA[k] = 0.0;
     }
     int stop_bits = 0;
     bool failed = false;
@@ -547,13 +574,14 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     }
     cs.publish(un0, un1);
     while (n < seg_end && !failed) {
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < RK; ++s) {
             if (!cs.exchange_u()) {
                 failed = true;
                 break;
             }
-            double r0[P], r1[P];
-            const int bits = cs.rhs(s == 0, r0, r1);
+            double r0[P], r1[P], w[P], rA[P];
+            const bool reint = EVA && s == 0 && (n % K) == 0;
+            const int bits = cs.template rhs<EVA>(s == 0, r0, r1, cvA, w, reint);
             if (bits < 0) {
                 failed = true;
                 break;
@@ -562,29 +590,100 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
                 stop_bits = bits;
                 break;
             }
-            const double c_next = (s == 2) ? dt : 0.5 * dt;
-            const double wacc = (s == 0 || s == 3) ? 1.0 : 2.0;
-            double us0[P], us1[P];
+            if (reint) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) unA[k] = cvA[k];
+            }
+            if constexpr (EVA) {
+                const auto tb = cs.tables();
+#pragma unroll
+                for (int k = 0; k < P; ++k) rA[k] = -2.0 * cs.tab(tb, 0, k) * cvA[k] * w[k] * cv0[k] * cv1[k];
+            }
+            if constexpr (RK == 4 && !EVA) {
+                // classical RK4 with the stage value as a per-stage temporary
+                const double c_next = (s == 2) ? dt : 0.5 * dt;
+                const double wacc = (s == 0 || s == 3) ? 1.0 : 2.0;
+                double us0[P], us1[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    if (s == 0) {
+                        acc0[k] = r0[k];
+                        acc1[k] = r1[k];
+                    } else {
+                        acc0[k] = acc0[k] + wacc * r0[k];
+                        acc1[k] = acc1[k] + wacc * r1[k];
+                    }
+                    if (s < 3) {
+                        us0[k] = un0[k] + c_next * r0[k];
+                        us1[k] = un1[k] + c_next * r1[k];
+                    } else {
+                        un0[k] = un0[k] + (dt / 6.0) * acc0[k];
+                        un1[k] = un1[k] + (dt / 6.0) * acc1[k];
+                        us0[k] = un0[k];
+                        us1[k] = un1[k];
+                    }
+                }
+                cs.publish(us0, us1);
+                continue;
+            }
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                if (s == 0) {
-                    acc0[k] = r0[k];
-                    acc1[k] = r1[k];
+                if constexpr (RK == 4) {
+                    const double c_next = (s == 2) ? dt : 0.5 * dt;
+                    const double wacc = (s == 0 || s == 3) ? 1.0 : 2.0;
+                    if (s == 0) {
+                        acc0[k] = r0[k];
+                        acc1[k] = r1[k];
+                        if (EVA) accA[k] = rA[k];
+                    } else {
+                        acc0[k] = acc0[k] + wacc * r0[k];
+                        acc1[k] = acc1[k] + wacc * r1[k];
+                        if (EVA) accA[k] = accA[k] + wacc * rA[k];
+                    }
+                    if (s < 3) {
+                        cv0[k] = un0[k] + c_next * r0[k];
+                        cv1[k] = un1[k] + c_next * r1[k];
+                        if (EVA) cvA[k] = unA[k] + c_next * rA[k];
+                    } else {
+                        un0[k] = un0[k] + (dt / 6.0) * acc0[k];
+                        un1[k] = un1[k] + (dt / 6.0) * acc1[k];
+                        if (EVA) unA[k] = unA[k] + (dt / 6.0) * accA[k];
+                    }
+                } else if constexpr (RK == 3) {
+                    if (s == 0) {
+                        cv0[k] = un0[k] + dt * r0[k];
+                        cv1[k] = un1[k] + dt * r1[k];
+                        if (EVA) cvA[k] = unA[k] + dt * rA[k];
+                    } else if (s == 1) {
+                        cv0[k] = 0.75 * un0[k] + 0.25 * (cv0[k] + dt * r0[k]);
+                        cv1[k] = 0.75 * un1[k] + 0.25 * (cv1[k] + dt * r1[k]);
+                        if (EVA) cvA[k] = 0.75 * unA[k] + 0.25 * (cvA[k] + dt * rA[k]);
+                    } else {
+                        un0[k] = un0[k] / 3.0 + (2.0 / 3.0) * (cv0[k] + dt * r0[k]);
+                        un1[k] = un1[k] / 3.0 + (2.0 / 3.0) * (cv1[k] + dt * r1[k]);
+                        if (EVA) unA[k] = unA[k] / 3.0 + (2.0 / 3.0) * (cvA[k] + dt * rA[k]);
+                    }
                 } else {
-                    acc0[k] = acc0[k] + wacc * r0[k];
-                    acc1[k] = acc1[k] + wacc * r1[k];
-                }
-                if (s < 3) {
-                    us0[k] = un0[k] + c_next * r0[k];
-                    us1[k] = un1[k] + c_next * r1[k];
-                } else {
-                    un0[k] = un0[k] + (dt / 6.0) * acc0[k];
-                    un1[k] = un1[k] + (dt / 6.0) * acc1[k];
-                    us0[k] = un0[k];
-                    us1[k] = un1[k];
+                    if (s == 0) {
+                        cv0[k] = un0[k] + dt * r0[k];
+                        cv1[k] = un1[k] + dt * r1[k];
+                        if (EVA) cvA[k] = unA[k] + dt * rA[k];
+                    } else {
+                        un0[k] = 0.5 * un0[k] + 0.5 * (cv0[k] + dt * r0[k]);
+                        un1[k] = 0.5 * un1[k] + 0.5 * (cv1[k] + dt * r1[k]);
+                        if (EVA) unA[k] = 0.5 * unA[k] + 0.5 * (cvA[k] + dt * rA[k]);
+                    }
                 }
             }
-            cs.publish(us0, us1);
+            if (s == RK - 1) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    cv0[k] = un0[k];
+                    cv1[k] = un1[k];
+                    cvA[k] = unA[k];
+                }
+            }
+            cs.publish(cv0, cv1);
         }
         if (stop_bits || failed) break;
         ++n;
@@ -594,6 +693,7 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
         if (cs.own(k)) {
             a.Phi[ic.off + i0 + k] = un0[k];
             a.Pi[ic.off + i0 + k] = un1[k];
+            if (EVA) a.A[ic.off + i0 + k] = unA[k];
         }
     }
     if (cs.g == 0 && cs.tid == 0) {
@@ -615,12 +715,12 @@ __global__ void big_reset_kernel(BigArgs x)
 {
     const int d = threadIdx.x;
     if (d < x.n_desc) {
-        x.desc[d].ctr[0] = 0ull;
-        x.desc[d].ctr[1] = 0ull;
+        x.ctr[2 * d] = 0ull;
+        x.ctr[2 * d + 1] = 0ull;
     }
 }
 
-template <int P, int W>
+template <int P, int W, int RK, bool EVA>
 hipError_t launch_big_t(int blocks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
 {
     if (x.n_desc < 1 || x.n_desc > 1024) return hipErrorInvalidValue;
@@ -631,30 +731,43 @@ hipError_t launch_big_t(int blocks, const EvolveArgs& a, const BigArgs& x, hipSt
     EvolveArgs ea = a;
     BigArgs xa = x;
     void* args[] = {(void*)&ea, (void*)&xa};
-    return hipLaunchCooperativeKernel((const void*)evolve_big_kernel<P, W>, dim3(blocks), dim3(64 * W), args, lds, s);
+    return hipLaunchCooperativeKernel((const void*)evolve_big_kernel<P, W, RK, EVA>, dim3(blocks), dim3(64 * W), args,
+                                      lds, s);
 }
 
-template <int P, int W>
+template <int P, int W, int RK, bool EVA>
 hipError_t capacity_t(int device, int* blocks)
 {
     int cus = 0, per_cu = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)evolve_big_kernel<P, W>, 64 * W,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)evolve_big_kernel<P, W, RK, EVA>, 64 * W,
                                                      big_lds_bytes_for<P, W>());
     if (e != hipSuccess) return e;
     *blocks = per_cu * cus;
     return hipSuccess;
 }
 
-template <int P, int W>
+template <int P, int W, int RK, bool EVA>
 hipError_t prepare_big_t(size_t max_lds)
 {
     const size_t need = big_lds_bytes_for<P, W>();
     if (need > max_lds) return hipErrorInvalidValue;
-    return hipFuncSetAttribute((const void*)evolve_big_kernel<P, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)need);
+    return hipFuncSetAttribute((const void*)evolve_big_kernel<P, W, RK, EVA>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
 }
+
+// The kernel variant of a scheme: RK order 2, 3 or 4, A solved or evolved.
+#define ADSCL_BIG_SCHEME(FN, p, w, ...)                                               \
+    do {                                                                              \
+        if (rk == 4 && !eva) return FN<p, w, 4, false>(__VA_ARGS__);                 \
+        if (rk == 4 && eva) return FN<p, w, 4, true>(__VA_ARGS__);                   \
+        if (rk == 3 && !eva) return FN<p, w, 3, false>(__VA_ARGS__);                 \
+        if (rk == 3 && eva) return FN<p, w, 3, true>(__VA_ARGS__);                   \
+        if (rk == 2 && !eva) return FN<p, w, 2, false>(__VA_ARGS__);                 \
+        if (rk == 2 && eva) return FN<p, w, 2, true>(__VA_ARGS__);                   \
+        return hipErrorInvalidValue;                                                  \
+    } while (0)
 
 }  // namespace
 
@@ -677,28 +790,29 @@ size_t big_lds_bytes(ClassCfg c)
            sizeof(double);
 }
 
-hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds)
+hipError_t prepare_evolve_big(ClassCfg c, int rk, bool eva, size_t max_lds)
 {
 #define X(p, w) \
-    if (c.P == p && c.W == w) return prepare_big_t<p, w>(max_lds);
+    if (c.P == p && c.W == w) ADSCL_BIG_SCHEME(prepare_big_t, p, w, max_lds);
     ADSCL_BIG_CLASSES(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_evolve_big(ClassCfg c, int blocks, const EvolveArgs& a, const BigArgs& x, hipStream_t s)
+hipError_t launch_evolve_big(ClassCfg c, int rk, bool eva, int blocks, const EvolveArgs& a, const BigArgs& x,
+                             hipStream_t s)
 {
 #define X(p, w) \
-    if (c.P == p && c.W == w) return launch_big_t<p, w>(blocks, a, x, s);
+    if (c.P == p && c.W == w) ADSCL_BIG_SCHEME(launch_big_t, p, w, blocks, a, x, s);
     ADSCL_BIG_CLASSES(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-hipError_t big_capacity(ClassCfg c, int device, int* blocks)
+hipError_t big_capacity(ClassCfg c, int rk, bool eva, int device, int* blocks)
 {
 #define X(p, w) \
-    if (c.P == p && c.W == w) return capacity_t<p, w>(device, blocks);
+    if (c.P == p && c.W == w) ADSCL_BIG_SCHEME(capacity_t, p, w, device, blocks);
     ADSCL_BIG_CLASSES(X)
 #undef X
     return hipErrorInvalidValue;

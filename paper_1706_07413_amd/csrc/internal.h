@@ -89,24 +89,30 @@ hipError_t launch_evolve_scheme(ClassCfg c, int rk, bool eva, bool full, int n_b
 struct BigDesc {
     int32_t inst;             // instance index
     int32_t chunks;           // G
-    int32_t first;            // its first workgroup in the launch
+    int32_t first;            // its first workgroup in the launch, and its first exchange record
     int32_t pad;
-    double* xch;              // exchange records [G][32]
-    unsigned long long* ctr;  // arrival counter, then the error flag (int)
 };
+// The pointers sit in the kernel arguments (not in the table) so that the
+// compiler knows they address global memory and emits global, not flat,
+// loads and atomics for the exchange records and counters.
 struct BigArgs {
     const BigDesc* desc;      // device [n_desc]
+    double* xch;              // exchange records [blocks][32], in launch order
+    unsigned long long* ctr;  // per instance: arrival counter, then the error flag (int) [n_desc][2]
     int32_t n_desc;
     int32_t pad;
 };
 bool big_class_supported(ClassCfg c);
 size_t big_lds_bytes(ClassCfg c);
-hipError_t prepare_evolve_big(ClassCfg c, size_t max_lds);
-// Workgroups of the multi-workgroup kernel in configuration c the device holds at once.
-hipError_t big_capacity(ClassCfg c, int device, int* blocks);
+// The multi-workgroup kernel of a scheme (rk: Runge-Kutta order 2, 3 or 4;
+// eva: A evolved by Eq. (4)) in chunk configuration c.
+hipError_t prepare_evolve_big(ClassCfg c, int rk, bool eva, size_t max_lds);
+// Workgroups of that kernel the device holds at once.
+hipError_t big_capacity(ClassCfg c, int rk, bool eva, int device, int* blocks);
 // One cooperative launch of `blocks` workgroups over the instances of x (all in
 // configuration c, sum of their chunks = blocks <= big_capacity).
-hipError_t launch_evolve_big(ClassCfg c, int blocks, const EvolveArgs& a, const BigArgs& x, hipStream_t s);
+hipError_t launch_evolve_big(ClassCfg c, int rk, bool eva, int blocks, const EvolveArgs& a, const BigArgs& x,
+                             hipStream_t s);
 constexpr int kBigMaxChunks = 96;
 
 // Initial data: Pi = (2 eps/pi) exp(-4 tan^2 x/(pi^2 sigma^2)), Phi = 0 (pins applied).

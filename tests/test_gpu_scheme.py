@@ -105,3 +105,34 @@ def test_scheme_options_refuse_the_adjoint():
         b.adjoint(np.array([0.5]), np.array([[1.0, 0.2, 0.0, 0.0]]), 4, 0.01, 8)
     assert e.value.code == adscl.EUNSUPPORTED
     b.close()
+
+
+@pytest.mark.parametrize("rk,K", [(3, 0), (3, 5), (2, 3), (4, 7)])
+def test_scheme_on_multi_workgroup_grids(rk, K):
+    """The scheme options on grids above 4097 points (chunks of 2048 points over
+    several workgroups; 10001 leaves a short last chunk) next to a small grid,
+    across a snapshot segment and a second call."""
+    import torch
+    Ns = [6145, 257, 10001]
+    eps = np.array([5.0, 3.0, 6.0])
+    sig = np.array([0.2, 0.25, 0.18])
+    b = adscl.Batch(Ns, a_collapse=0.0, rk_order=rk, a_reint=K)
+    b.init_gaussian(eps, sig)
+    n1, n2, every, slots = 120, 157, 40, 4
+    snaps = torch.zeros((slots, 5, b.total), dtype=torch.float64, device="cuda")
+    b.step(n1, 1e9, snap_every=every, snaps=snaps)
+    sn = snaps.cpu().numpy()
+    b.step(n2 - n1, 1e9)
+    st = {k: v.cpu().numpy() for k, v in b.get_state().items()}
+    s = b.status()
+    b.close()
+    for i, N in enumerate(Ns):
+        Phi, Pi = O.init_gaussian(N, eps[i], sig[i])
+        r1 = O.evolve_scheme(Phi, Pi, n1, rk=rk, a_reint=K, snap_every=every, n_slots=slots)
+        for sl in range(slots):
+            for f in range(5):
+                check(b.split(sn[sl, f])[i], r1["snaps"][sl, f], "rk%d K%d N=%d slot %d %s" % (rk, K, N, sl, FIELDS[f]))
+        r2 = O.evolve_scheme(r1["Phi"], r1["Pi"], n2, n0=n1, A=r1["A"], rk=rk, a_reint=K)
+        assert s["steps"][i] == r2["steps"] == n2
+        for f in FIELDS:
+            check(b.split(st[f])[i], r2[f], "rk%d K%d N=%d %s" % (rk, K, N, f))
