@@ -75,6 +75,7 @@ struct Chunk {
     double h24, i12h, kof, thr;
     const ADSCL_GLOBAL double* tabI;  // tables of the whole instance, [g][3][P][NL]
     const ADSCL_GLOBAL double* tab0;  // this chunk's
+    double tabL, tabR;                 // table 0 at points a - 1 (thread 0) and a + C (the last thread)
     double* xg;                        // exchange records [G][XREC]
     unsigned long long* ctr;
     int* err;
@@ -275,7 +276,7 @@ struct Chunk {
                 pl = -red[4 * W];
             } else {
                 const double2 u = U[(P - 1) * RS];  // point a - 1
-                pl = tab_at(0, a - 1) * (u.x * u.x + u.y * u.y);
+                pl = tabL * (u.x * u.x + u.y * u.y);
             }
             if (tid < NL - 1) {
                 pr = PE[tid + 1];
@@ -283,7 +284,7 @@ struct Chunk {
                 pr = 0.0;
             } else {
                 const double2 u = U[NL + 1];  // point a + C
-                pr = tab_at(0, a + C) * (u.x * u.x + u.y * u.y);
+                pr = tabR * (u.x * u.x + u.y * u.y);
             }
             double sg[P], dp[P];
             double R = carry, stot = 0.0;
@@ -323,32 +324,49 @@ struct Chunk {
             }
             if (tid == NL - 1 && !last) rec(g)[XS_SL] = sg[P - 1];
             if (!grid_sync()) return -1;
-            // per-chunk factors F_h and the sigma carry D_g
-            double* fac = red + 4 * W + 8;  // [0,G) F_h, [G,2G) F_h * (sigma' total of h)
-            {
-                const double p1 = rec(0)[XS_P1];
-                double tp = 0.0;
-                for (int c = 0; c < G; ++c) tp += rec(c)[XS_P];
-                const double pN2 = rec(G - 1)[XS_PN];
-                const double dN = -h24 * (24.0 * tp + 2.0 * pN2 + 2.0 * p1);
-                const double shift = bgauge ? dN : 0.0;
-                if (tid < G) {
-                    double Cg = 0.0;
-                    for (int c = 0; c < tid; ++c) Cg += rec(c)[XS_P];
-                    const double Fh = exp(24.0 * h24 * Cg + 2.0 * h24 * p1 + shift);
-                    fac[tid] = Fh;
-                    fac[G + tid] = Fh * rec(tid)[XS_S];
+            // per-chunk factors F_h and the sigma carry D_g.  The records are
+            // read once, thread h reading chunk h's, so that the reads after
+            // the barrier cost one memory latency rather than one per chunk.
+            double* fac = red + 4 * W + 8;  // [0,G) F_h, [G,2G) sigma' total of h, then D_h, [2G,3G) p total of h
+            if (tid < G) {
+                const double* r = rec(tid);
+                fac[2 * G + tid] = r[XS_P];
+                fac[G + tid] = r[XS_S];
+            }
+            if (tid == 0) {
+                red[4 * W + 3] = rec(0)[XS_P1];
+                red[4 * W + 4] = rec(G - 1)[XS_PN];
+                if (!first && solveS) red[4 * W + 5] = rec(g - 1)[XS_SL];
+            }
+            if (tid == NL - 1 && !last && solveS) red[4 * W + 6] = rec(g + 1)[XS_SF];
+            __syncthreads();
+            if (wv == 0) {
+                // lane h (< G <= 64) for chunk h: the p carry C_h and grid total
+                // by a wavefront scan, F_h, then the sigma carry D_h = sum over
+                // c < h of F_c (sigma' total of c) by a second scan
+                const double p1 = red[4 * W + 3];
+                const double v = (lane < G) ? fac[2 * G + lane] : 0.0;
+                const double inc = wave_incl_scan(v);
+                const double tp = __shfl(inc, 63);
+                const double Cg = inc - v;
+                const double dNg = -h24 * (24.0 * tp + 2.0 * red[4 * W + 4] + 2.0 * p1);
+                const double shift = bgauge ? dNg : 0.0;
+                const double Fh = exp(24.0 * h24 * Cg + 2.0 * h24 * p1 + shift);
+                const double fs = (lane < G) ? Fh * fac[G + lane] : 0.0;
+                const double inc2 = wave_incl_scan(fs);
+                if (lane < G) {
+                    fac[lane] = Fh;
+                    fac[G + lane] = inc2 - fs;
                 }
-                if (tid == 0) red[4 * W + 2] = dN;
+                if (lane == 0) red[4 * W + 2] = dNg;
             }
             __syncthreads();
             const double Fg = fac[g];
-            double Dg = 0.0;
-            for (int c = 0; c < g; ++c) Dg += fac[G + c];
+            const double Dg = fac[G + g];
             const double sl = !solveS ? 0.0 : (tid > 0) ? SE[NL + tid - 1]
-                                        : (first ? sg[1] : rec(g - 1)[XS_SL] * fac[g - 1] / Fg);
+                                        : (first ? sg[1] : red[4 * W + 5] * fac[g - 1] / Fg);
             const double sr = !solveS ? 0.0 : (tid < NL - 1) ? SE[tid + 1]
-                                        : (last ? 0.0 : rec(g + 1)[XS_SF] * fac[g + 1] / Fg);
+                                        : (last ? 0.0 : red[4 * W + 6] * fac[g + 1] / Fg);
             {
                 double R2 = carry2;
 #pragma unroll
@@ -435,8 +453,14 @@ struct Chunk {
         }
         if (!grid_sync()) return -1;  // sync C
         if (check) {
-            int b = 0;
-            for (int c = 0; c < G; ++c) b |= (int)rec(c)[XF_B];
+            // the first wavefront gathers the chunks' bits, lane h reading chunk h's (G <= 64)
+            if (wv == 0) {
+                const int bl = (lane < G) ? (int)rec(lane)[XF_B] : 0;
+                const int bb = (__any(bl & 1) ? 1 : 0) | (__any(bl & 2) ? 2 : 0);
+                if (lane == 0) red[3 * W] = (double)bb;
+            }
+            __syncthreads();
+            const int b = (int)red[3 * W];
             if (b) return b;
         }
         if (tid == 0 && !first) {
@@ -491,7 +515,7 @@ struct Chunk {
 template <int P, int W>
 constexpr size_t big_lds_bytes_for()
 {
-    return (StageLayout<P, W>::lds_doubles + (size_t)3 * 64 + (size_t)3 * P * 64 * W) * sizeof(double);
+    return (StageLayout<P, W>::lds_doubles + (size_t)3 * kBigMaxChunks + (size_t)3 * P * 64 * W) * sizeof(double);
 }
 
 // RK: Runge-Kutta order (4 classical; 3 and 2 the Shu-Osher methods, as the
@@ -539,8 +563,10 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.thr = a.a_collapse;
     cs.tabI = gmem(a.tab[b]);
     cs.tab0 = cs.tabI + (size_t)cs.g * 3 * Ch::C;
+    cs.tabL = (!cs.first && cs.tid == 0) ? cs.tab_at(0, cs.a - 1) : 0.0;
+    cs.tabR = (!cs.last && cs.tid == Ch::NL - 1) ? cs.tab_at(0, cs.a + Ch::C) : 0.0;
     // each lane copies exactly the table entries it reads later: no barrier
-    cs.T = cs.red + 4 * W + 8 + 3 * 64;
+    cs.T = cs.red + 4 * W + 8 + 3 * kBigMaxChunks;
 #pragma unroll
     for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
     cs.xg = x.xch + (size_t)bd.first * XREC;
@@ -786,7 +812,7 @@ bool big_class_supported(ClassCfg c)
 
 size_t big_lds_bytes(ClassCfg c)
 {
-    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * 64 + 3 * c.P * 64 * c.W) *
+    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * kBigMaxChunks + 3 * c.P * 64 * c.W) *
            sizeof(double);
 }
 

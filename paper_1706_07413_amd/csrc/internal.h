@@ -113,7 +113,9 @@ hipError_t big_capacity(ClassCfg c, int rk, bool eva, int device, int* blocks);
 // configuration c, sum of their chunks = blocks <= big_capacity).
 hipError_t launch_evolve_big(ClassCfg c, int rk, bool eva, int blocks, const EvolveArgs& a, const BigArgs& x,
                              hipStream_t s);
-constexpr int kBigMaxChunks = 96;
+// At most 64 chunks: the kernel keeps three per-chunk factors in 3 * 64 LDS
+// slots and gathers the chunks' collapse bits with one wavefront.
+constexpr int kBigMaxChunks = 64;
 
 // Initial data: Pi = (2 eps/pi) exp(-4 tan^2 x/(pi^2 sigma^2)), Phi = 0 (pins applied).
 hipError_t launch_init_gaussian(int n_inst, const InstConst* ic, const double* eps, const double* sigma,
