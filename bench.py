@@ -251,10 +251,16 @@ def paper_table_rates(adscl, steps=2048):
     """The single-instance workloads of the paper's speed tables, on this GPU:
     the dynamic metric at N = 32769 and the frozen metric (A = 1, delta = 0,
     the linear wave) at N = 65537, two-mode data 0.05 (e_0 + 0.6 e_1), a window
-    of `steps` RK4 steps after 64 warm-up steps."""
+    of `steps` steps after 64 warm-up steps: classical RK4, and at N = 32769
+    also the paper's RK3, with A solved at every stage and with A evolved by
+    Eq. (4) and re-integrated every 16 steps."""
     out = {}
-    for name, N, flags in (("dynamic_N32769", 32769, 0), ("frozen_N65537", 65537, adscl.FROZEN_METRIC)):
-        b = adscl.Batch([N], a_collapse=0.01, n_modes=2, flags=flags)
+    legs = (("dynamic_N32769", 32769, 0, 4, 0), ("frozen_N65537", 65537, adscl.FROZEN_METRIC, 4, 0),
+            # the paper's own integrator (RK3), A solved at every stage and A
+            # evolved by Eq. (4) with re-integration every 16 steps
+            ("dynamic_N32769_rk3", 32769, 0, 3, 0), ("dynamic_N32769_rk3_evolvedA_K16", 32769, 0, 3, 16))
+    for name, N, flags, rk, K in legs:
+        b = adscl.Batch([N], a_collapse=0.01, n_modes=2, flags=flags, rk_order=rk, a_reint=K)
         b.init_modes(np.array([0.05]), np.array([[1.0, 0.6]]))
         b.step(64, 1e9)
         b.sync()
@@ -263,7 +269,8 @@ def paper_table_rates(adscl, steps=2048):
         b.sync()
         dt = time.perf_counter() - t0
         b.close()
-        out[name] = {"pt_steps_per_s": N * steps / dt, "us_per_step": dt / steps * 1e6, "steps": steps}
+        out[name] = {"pt_steps_per_s": N * steps / dt, "us_per_step": dt / steps * 1e6, "steps": steps,
+                     "rk_order": rk, "a_reint": K}
     return out
 
 
@@ -398,6 +405,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4096, help="RK4 steps per instance of that sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the large-grid legs (the 16385-point instance, eight side by side, the speed-table grids)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient-rate leg")
     ap.add_argument("--adjoint-t", type=float, default=1.0, help="time window of the adjoint leg")
     ap.add_argument("--config1-full", action="store_true",
@@ -463,6 +472,9 @@ def main():
         eps_values = [float(e) for e in args.qp_eps.split(",")]
         print(json.dumps({"qp_sweep": qp_sweep(adscl, args.qp_n, eps_values, args.qp_tmax, args.qp_rk,
                                                args.qp_reint)}))
+        return
+    if args.large_only:
+        print(json.dumps({"large_instance": large_instance_rate(adscl), "paper_tables": paper_table_rates(adscl)}))
         return
     if args.config1_full:
         print(json.dumps({"config1_full": config1_full(adscl, spectra_out=args.spectra_out)}))

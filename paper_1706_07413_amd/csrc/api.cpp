@@ -48,7 +48,7 @@ struct BigGroup {
     std::vector<int> cls;
     BigDesc* d_desc = nullptr;
     double* xch = nullptr;              // exchange records [blocks][32]
-    unsigned long long* ctr = nullptr;  // [cls.size()][2]: arrival counter, error flag
+    unsigned long long* ctr = nullptr;  // [cls.size()][kBigCtrStride]: arrival counter, error flag
 };
 
 // Host-side tables of one grid size N.
@@ -504,13 +504,13 @@ int run_call(adscl_ctx* c, int64_t max_steps, double t_end, int32_t snap_every, 
 int check_big(adscl_ctx* c)
 {
     for (const BigGroup& g : c->big_groups) {
-        std::vector<unsigned long long> ctr(2 * g.cls.size());
+        std::vector<unsigned long long> ctr(kBigCtrStride * g.cls.size());
         HIP_TRY(c, hipMemcpyAsync(ctr.data(), g.ctr, sizeof(unsigned long long) * ctr.size(), hipMemcpyDeviceToHost,
                                   c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         for (size_t d = 0; d < g.cls.size(); ++d) {
             int e = 0;
-            std::memcpy(&e, &ctr[2 * d + 1], sizeof(int));
+            std::memcpy(&e, &ctr[d * kBigCtrStride + 1], sizeof(int));
             if (e)
                 return fail(c, ADSCL_EHIP, "instance " + std::to_string(c->classes[g.cls[d]].inst[0]) +
                                                ": a grid synchronisation of its workgroups timed out");
@@ -1052,8 +1052,8 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
         TRY_C(hipMalloc((void**)&g.d_desc, sizeof(BigDesc) * desc.size()));
         TRY_C(hipMemcpy(g.d_desc, desc.data(), sizeof(BigDesc) * desc.size(), hipMemcpyHostToDevice));
         TRY_C(hipMalloc((void**)&g.xch, sizeof(double) * 32 * (size_t)g.blocks));
-        TRY_C(hipMalloc((void**)&g.ctr, sizeof(unsigned long long) * 2 * desc.size()));
-        TRY_C(hipMemset(g.ctr, 0, sizeof(unsigned long long) * 2 * desc.size()));
+        TRY_C(hipMalloc((void**)&g.ctr, sizeof(unsigned long long) * kBigCtrStride * desc.size()));
+        TRY_C(hipMemset(g.ctr, 0, sizeof(unsigned long long) * kBigCtrStride * desc.size()));
     }
 
     std::vector<const double*> tabp(c->n_inst), ep(c->n_inst), wpp(c->n_inst), wfp(c->n_inst);

@@ -570,8 +570,8 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
 #pragma unroll
     for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
     cs.xg = x.xch + (size_t)bd.first * XREC;
-    cs.ctr = x.ctr + 2 * d;
-    cs.err = reinterpret_cast<int*>(x.ctr + 2 * d + 1);
+    cs.ctr = x.ctr + (size_t)d * kBigCtrStride;
+    cs.err = reinterpret_cast<int*>(x.ctr + (size_t)d * kBigCtrStride + 1);
     cs.target = 0;
     const double dt = ic.dt;
     const int i0 = cs.i0;
@@ -741,8 +741,8 @@ __global__ void big_reset_kernel(BigArgs x)
 {
     const int d = threadIdx.x;
     if (d < x.n_desc) {
-        x.ctr[2 * d] = 0ull;
-        x.ctr[2 * d + 1] = 0ull;
+        x.ctr[(size_t)d * kBigCtrStride] = 0ull;
+        x.ctr[(size_t)d * kBigCtrStride + 1] = 0ull;
     }
 }
 

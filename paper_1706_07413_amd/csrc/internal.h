@@ -98,7 +98,7 @@ struct BigDesc {
 struct BigArgs {
     const BigDesc* desc;      // device [n_desc]
     double* xch;              // exchange records [blocks][32], in launch order
-    unsigned long long* ctr;  // per instance: arrival counter, then the error flag (int) [n_desc][2]
+    unsigned long long* ctr;  // per instance: arrival counter, then the error flag (int) [n_desc][kBigCtrStride]
     int32_t n_desc;
     int32_t pad;
 };
@@ -116,6 +116,9 @@ hipError_t launch_evolve_big(ClassCfg c, int rk, bool eva, int blocks, const Evo
 // At most 64 chunks: the kernel keeps three per-chunk factors in 3 * 64 LDS
 // slots and gathers the chunks' collapse bits with one wavefront.
 constexpr int kBigMaxChunks = 64;
+// 64-bit words between two instances' barrier counters: one 256-byte block
+// each, so that the instances of a launch do not poll and count on one line.
+constexpr int kBigCtrStride = 32;
 
 // Initial data: Pi = (2 eps/pi) exp(-4 tan^2 x/(pi^2 sigma^2)), Phi = 0 (pins applied).
 hipError_t launch_init_gaussian(int n_inst, const InstConst* ic, const double* eps, const double* sigma,
