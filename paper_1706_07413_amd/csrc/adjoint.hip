@@ -471,16 +471,11 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
         {
             const ADSCL_GLOBAL double* u = gmem(a.seg[b]) + (size_t)(t - sq.n0) * 2 * (size_t)N;
             double un0[P], un1[P];
-            {
-                const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    const bool o = sg.own(k);
-                    un0[k] = o ? u[i0 + k] : 0.0;
-                    un1[k] = o ? u[N + i0 + k] : 0.0;
-                    sv.st(0, k, un0[k]);
-                    sv.st(1, k, un1[k]);
-                }
+            for (int k = 0; k < P; ++k) {
+                const bool o = sg.own(k);
+                un0[k] = o ? u[i0 + k] : 0.0;
+                un1[k] = o ? u[N + i0 + k] : 0.0;
             }
             // the reverse sweep's last readers of the LDS edges are done
             __syncthreads();
@@ -494,16 +489,14 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
 #pragma unroll 1
             for (int s = 0; s < 4; ++s) {
                 double r0[P], r1[P];
+                // stores V_s, e^-delta and S of the stage to fields 4 s .. 4 s + 3
                 sg.template rhs<true>(false, false, cv0, cv1, r0, r1, stg, 4 * s + 2);
                 if (s < 3) {
                     const double c_next = (s == 2) ? dt : 0.5 * dt;
-                    const auto sv = lane_arr<P, NL>(stg, tid);
 #pragma unroll
                     for (int k = 0; k < P; ++k) {
                         cv0[k] = un0[k] + c_next * r0[k];
                         cv1[k] = un1[k] + c_next * r1[k];
-                        sv.st(4 * (s + 1), k, cv0[k]);
-                        sv.st(4 * (s + 1) + 1, k, cv1[k]);
                     }
                     sg.publish(cv0, cv1);
                 }

@@ -566,7 +566,8 @@ struct Stage {
     // run before B3 and the function returns their workgroup-wide bits
     // (1 collapsed, 2 non-finite) without computing r when any is set.
     // r0, r1: Phi_t, Pi_t of the own points (0 at pinned points).  KEEP: also
-    // stores e^-delta and S of the lane's points to fields fE and fE + 1 of ES.
+    // stores the stage input (v0, v1), e^-delta and S of the lane's points to
+    // fields fE - 2 .. fE + 1 of ES.
     // v0, v1: the published stage input of the own points (read on the edge
     // path, where it is not in LDS).
     // EVA (A evolved by Eq. (4), the paper's alternative to solving Eq. (5) at
@@ -616,14 +617,6 @@ struct Stage {
         } else {
 #pragma unroll
             for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
-        }
-        if constexpr (KEEP) {
-            const auto es = lane_arr<P, NL>(ES, tid);
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                es.st(fE, k, E[k]);
-                es.st(fE + 1, k, S[k]);
-            }
         }
 
         // fluxes; c3s and tan^2 x are 0 at x = 0 in the tables, so w_0 = E_0, g_0 = 0
@@ -685,6 +678,18 @@ struct Stage {
             const int wcol = __any(cl & 1) ? 1 : 0;
             const int wnf = __any(cl & 2) ? 2 : 0;
             if (lane == 0) red[2 * W + wv] = (double)(wcol | wnf);
+        }
+        if constexpr (KEEP) {
+            // after the flux loop, so that its table loads do not wait for
+            // these stores (vector loads and stores retire in issue order)
+            const auto es = lane_arr<P, NL>(ES, tid);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                es.st(fE - 2, k, v0[k]);
+                es.st(fE - 1, k, v1[k]);
+                es.st(fE, k, E[k]);
+                es.st(fE + 1, k, S[k]);
+            }
         }
         __syncthreads();  // B3
         if (check) {
@@ -762,14 +767,6 @@ struct Stage {
 #pragma unroll
             for (int k = 0; k < P; ++k) { dl[k] = 0.0; E[k] = 1.0; S[k] = 0.0; }
         }
-        if constexpr (KEEP) {
-            const auto es = lane_arr<P, NL>(ES, tid);
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                es.st(fE, k, E[k]);
-                es.st(fE + 1, k, S[k]);
-            }
-        }
         double ff[P], fg[P], chk = 0.0, f2_1 = 0.0, f2_2 = 0.0;
         int cl = 0;
 #pragma unroll
@@ -822,6 +819,18 @@ struct Stage {
             const int wcol = __any(cl & 1) ? 1 : 0;
             const int wnf = __any(cl & 2) ? 2 : 0;
             if (lane == 0) red[2 * W + wv] = (double)(wcol | wnf);
+        }
+        if constexpr (KEEP) {
+            // after the flux loop, so that its table loads do not wait for
+            // these stores (vector loads and stores retire in issue order)
+            const auto es = lane_arr<P, NL>(ES, tid);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                es.st(fE - 2, k, v0[k]);
+                es.st(fE - 1, k, v1[k]);
+                es.st(fE, k, E[k]);
+                es.st(fE + 1, k, S[k]);
+            }
         }
         __syncthreads();  // B3
         if (check) {
