@@ -120,11 +120,14 @@ def test_frozen_metric_on_chunked_grids(Ns, n):
         assert np.all(b.split(st["delta"])[i] == 0.0)
 
 
-@pytest.mark.parametrize("N,frozen,n", [(10001, False, 200), (16385, False, 120), (65537, True, 24)])
+@pytest.mark.parametrize("N,frozen,n", [(10001, False, 200), (16385, False, 120), (65537, True, 24),
+                                        (65537, False, 24)])
 def test_chunks_of_1024_points(monkeypatch, N, frozen, n):
     """The other chunk shape of the multi-workgroup kernel, (4, 4): 1024 points
     per workgroup (10001: nine full chunks and 784 points in the last; 65537:
-    64 chunks), selected with ADSCL_TUNE at context creation."""
+    64 chunks, the most a launch takes, so that the chunk carries fill every
+    lane of the wavefront that scans them), selected with ADSCL_TUNE at context
+    creation."""
     monkeypatch.setenv("ADSCL_TUNE", "%d:4x4" % N)
     c = np.array([[1.0, 0.6, -0.2]])
     eps = 0.3 if frozen else 0.05
