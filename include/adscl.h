@@ -189,9 +189,16 @@ int adscl_spectrum_snaps(adscl_ctx* ctx, int32_t J, int32_t n_slots, const doubl
  * map, constraint solves at every RK stage, stencils, RK4 stages, spectrum;
  * the collapse tests are piecewise constant and contribute nothing).  The state
  * is stored every ckpt_every steps on the way forward and each segment is
- * recomputed before it is reversed; device memory per instance is about
- * 16 N_b (n_final_b / ckpt_every + ckpt_every) bytes plus 150 N_b bytes of
- * stage scratch, held by the context for reuse.
+ * recomputed before it is reversed.  The recompute keeps every step's stage
+ * values (each RK stage's input, e^-delta and S: 128 N_b bytes per step) for
+ * the reverse sweep when those records, about 128 N_b min(ckpt_every,
+ * n_final_b) bytes summed over the instances, take at most a quarter of the
+ * device memory; otherwise (or when the environment variable
+ * ADSCL_ADJOINT_RECOMPUTE is set to a value other than 0) it keeps only each
+ * step's state, 16 N_b ckpt_every bytes, and the reverse sweep recomputes the
+ * stages from it.  Further device memory per instance: 16 N_b n_final_b /
+ * ckpt_every bytes of checkpoints and 160 N_b bytes of scratch.  All of it is
+ * held by the context for reuse.
  * Inputs: eps [n_inst], c [n_inst x Jc] row-major, 1 <= Jc <= n_modes,
  * 1 <= J <= n_modes, T >= 0 finite, ckpt_every >= 1.  Outputs: L [n_inst],
  * dLdc [n_inst x Jc], valid [n_inst] (int32): 1 when the instance reached t_n

@@ -11,10 +11,13 @@
 //
 // Layout and launch shape are those of the forward kernel (stage.h): one
 // workgroup per instance, lane l owns points l*P .. l*P+P-1, lane-interleaved
-// LDS rows.  For each step t (in reverse) the kernel recomputes the four stage
-// inputs V_s from the stored U^t, keeping V_s, e^-delta and S of every stage in
-// a per-instance scratch (lane-interleaved, so each lane reads back only what
-// it wrote), then runs the four stage adjoints in reverse.
+// LDS rows.  For each step t (in reverse) the kernel takes the four stage
+// inputs V_s with their e^-delta and S from the stage record that the forward
+// recompute of the segment kept (the forward kernel's own arithmetic, its
+// tables in LDS), or, where the records would not fit, recomputes them from
+// the stored U^t into a per-instance scratch; both are lane-interleaved, so
+// each lane reads back only what it (or its forward counterpart) wrote.  Then
+// it runs the four stage adjoints in reverse.
 #include <math.h>
 
 #include "stage.h"
@@ -460,6 +463,9 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
         ub_st(3, k, o ? a.Ubar[a.total + ic.off + i0 + k] : 0.0);
     }
 
+    // the segment's stage record, when the forward recompute kept one
+    constexpr size_t kRec = (size_t)16 * P * NL;
+    ADSCL_GLOBAL double* const rec = a.keep ? gmem(a.keep[b]) : nullptr;
     for (int64_t t = sq.n1 - 1; t >= sq.n0; --t) {
         // the adjoint state at the start of this step's reverse, U-bar'
 #pragma unroll
@@ -467,8 +473,10 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
             ub_st(0, k, ub_ld(2, k));
             ub_st(1, k, ub_ld(3, k));
         }
-        // forward: the stage inputs V_s of step t and their e^-delta and S
-        {
+        // the stage inputs V_s of step t and their e^-delta and S: read from the
+        // record, or recomputed from U^t into the scratch
+        ADSCL_GLOBAL double* const st = rec ? rec + (size_t)(t - sq.n0) * kRec : stg;
+        if (!rec) {
             const ADSCL_GLOBAL double* u = gmem(a.seg[b]) + (size_t)(t - sq.n0) * 2 * (size_t)N;
             double un0[P], un1[P];
 #pragma unroll
@@ -513,7 +521,7 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
 #pragma unroll 1
         for (int s = 3; s >= 0; --s) {
             double vb0[P], vb1[P];
-            R::stage_reverse(sg, stg, 4 * s, kb0, kb1, vb0, vb1);
+            R::stage_reverse(sg, st, 4 * s, kb0, kb1, vb0, vb1);
             const double cs = (s == 3) ? dt : 0.5 * dt;
             const double bp = (s == 1) ? dt / 6.0 : dt / 3.0;
 #pragma unroll
@@ -802,6 +810,7 @@ hipError_t prepare_adj_t(size_t max_lds)
     X(16, 4)
 
 size_t adjoint_scratch_len(ClassCfg c) { return (size_t)kFields * c.P * 64 * c.W; }
+size_t stage_record_len(ClassCfg c) { return (size_t)16 * c.P * 64 * c.W; }
 
 hipError_t prepare_adjoint(ClassCfg c, size_t max_lds)
 {

@@ -370,6 +370,7 @@ EvolveArgs evolve_args(adscl_ctx* c, int32_t snap_every)
     a.status = c->d_status;
     a.src = nullptr;
     a.ckpt = nullptr;
+    a.keep = nullptr;
     a.total = c->total;
     a.a_collapse = c->thr;
     a.snap_every = snap_every;
@@ -559,6 +560,8 @@ struct AdjPlan {
     double** d_ckp = nullptr;
     double** d_segp = nullptr;
     double** d_stgp = nullptr;
+    double** d_keepp = nullptr;  // the segments' stage records, when kept (`stored`)
+    bool stored = false;
     InstStatus* rst = nullptr;
     AdjSeg* sgs = nullptr;
 };
@@ -569,7 +572,7 @@ int adj_plan(adscl_ctx* c, double T, int64_t K, int J, AdjPlan& pl)
 {
     const int n = c->n_inst;
     int rc;
-    std::vector<int64_t> nf(n), ck_off(n + 1), seg_off(n + 1), stg_off(n + 1);
+    std::vector<int64_t> nf(n), ck_off(n + 1), seg_off(n + 1), stg_off(n + 1), keep_off(n + 1);
     pl.J = J;
     pl.K = K;
     pl.max_seg = 0;
@@ -580,18 +583,34 @@ int adj_plan(adscl_ctx* c, double T, int64_t K, int J, AdjPlan& pl)
         ck_off[b + 1] = ck_off[b] + (nf[b] / K + 1) * 2 * (int64_t)c->N[b];
         seg_off[b + 1] = seg_off[b] + (std::min<int64_t>(K, nf[b]) + 1) * 2 * (int64_t)c->N[b];
         stg_off[b + 1] = stg_off[b] + (int64_t)adjoint_scratch_len(t.cfg);
+        keep_off[b + 1] = keep_off[b] + std::min<int64_t>(K, nf[b]) * (int64_t)stage_record_len(t.cfg);
         pl.max_seg = std::max<int64_t>(pl.max_seg, (nf[b] + K - 1) / K);
     }
-    void *ck, *seg, *stg, *ub, *u0, *dummy, *spec, *ptrs, *rst, *sgs;
+    // Keep each segment's stage record from the forward recompute (the reverse
+    // kernel then reads the stages instead of recomputing them) when the
+    // records take at most a quarter of the device memory; ADSCL_ADJOINT_RECOMPUTE
+    // set to a value other than 0 always recomputes.
+    {
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(c, hipMemGetInfo(&free_b, &total_b));
+        const char* env = std::getenv("ADSCL_ADJOINT_RECOMPUTE");
+        const bool force = env && env[0] && std::strcmp(env, "0") != 0;
+        pl.stored = !force && sizeof(double) * (size_t)keep_off[n] <= total_b / 4;
+    }
+    void *ck, *seg, *stg, *keep = nullptr, *ub, *u0, *dummy, *spec, *ptrs, *rst, *sgs;
     const size_t nJ = (size_t)n * J;
     if ((rc = buffer(c, "ckpt", sizeof(double) * ck_off[n], &ck))) return rc;
+    if (pl.stored) {
+        if ((rc = buffer(c, "keep", sizeof(double) * keep_off[n], &keep))) return rc;
+        seg_off.assign(n + 1, 0);  // no per-step states needed
+    }
     if ((rc = buffer(c, "seg", sizeof(double) * seg_off[n], &seg))) return rc;
     if ((rc = buffer(c, "stage", sizeof(double) * stg_off[n], &stg))) return rc;
     if ((rc = buffer(c, "ubar", sizeof(double) * 2 * c->total, &ub))) return rc;
     if ((rc = buffer(c, "u0", sizeof(double) * 2 * c->total, &u0))) return rc;
     if ((rc = buffer(c, "dummy", sizeof(double) * 2 * c->total, &dummy))) return rc;
     if ((rc = buffer(c, "spec", sizeof(double) * 6 * nJ, &spec))) return rc;
-    if ((rc = buffer(c, "ptrs", sizeof(double*) * 3 * n, &ptrs))) return rc;
+    if ((rc = buffer(c, "ptrs", sizeof(double*) * 4 * n, &ptrs))) return rc;
     if ((rc = buffer(c, "rstatus", sizeof(InstStatus) * n, &rst))) return rc;
     if ((rc = buffer(c, "segs", sizeof(AdjSeg) * n, &sgs))) return rc;
     pl.ub = (double*)ub;
@@ -606,16 +625,18 @@ int adj_plan(adscl_ctx* c, double T, int64_t K, int J, AdjPlan& pl)
     pl.d_ckp = (double**)ptrs;
     pl.d_segp = pl.d_ckp + n;
     pl.d_stgp = pl.d_segp + n;
+    pl.d_keepp = pl.d_stgp + n;
     pl.rst = (InstStatus*)rst;
     pl.sgs = (AdjSeg*)sgs;
-    std::vector<double*> hp(3 * n);
+    std::vector<double*> hp(4 * n);
     for (int b = 0; b < n; ++b) {
         hp[b] = (double*)ck + ck_off[b];
         hp[n + b] = (double*)seg + seg_off[b];
         hp[2 * n + b] = (double*)stg + stg_off[b];
+        hp[3 * n + b] = pl.stored ? (double*)keep + keep_off[b] : nullptr;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipMemcpy(ptrs, hp.data(), sizeof(double*) * 3 * n, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(ptrs, hp.data(), sizeof(double*) * 4 * n, hipMemcpyHostToDevice));
     if ((rc = spec_rows(c, 1))) return rc;
     return upload_ic(c, T);
 }
@@ -684,14 +705,16 @@ int adj_enqueue(adscl_ctx* c, const AdjPlan& pl, const double* d_eps, const doub
     ra.status = pl.rst;
     ra.src = pl.d_ckp;
     ra.src_every = (int32_t)pl.K;
-    ra.ckpt = pl.d_segp;
-    ra.ckpt_every = 1;
+    ra.ckpt = pl.stored ? nullptr : pl.d_segp;
+    ra.ckpt_every = pl.stored ? 0 : 1;
+    ra.keep = pl.stored ? pl.d_keepp : nullptr;
     AdjointArgs aa;
     aa.ic = c->d_ic;
     aa.order = nullptr;
     aa.tab = c->d_tab;
     aa.seg = pl.d_segp;
     aa.stg = pl.d_stgp;
+    aa.keep = pl.stored ? pl.d_keepp : nullptr;
     aa.sg = pl.sgs;
     aa.Ubar = pl.ub;
     aa.total = c->total;

@@ -34,7 +34,8 @@
 namespace adscl {
 namespace {
 
-template <int P, int W, bool FULL>
+// KEEP: also writes the stage record of every step (EvolveArgs::keep).
+template <int P, int W, bool FULL, bool KEEP>
 __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
 {
     extern __shared__ double lds[];
@@ -72,9 +73,12 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     // One RK4 stage on the published stage input; returns true when stage 0
     // finds the instance collapsed or non-finite (nothing is updated then).
     int stop_bits = 0;
+    constexpr size_t kRec = (size_t)16 * P * 64 * W;  // doubles of one step's stage record
+    ADSCL_GLOBAL double* const kp = KEEP ? gmem(a.keep[b]) : nullptr;
+    ADSCL_GLOBAL double* krec = nullptr;  // the current step's record
     auto stage = [&](const int s) -> bool {
         double r0[P], r1[P];
-        const int bits = sg.rhs(s == 0, frozen, cv0, cv1, r0, r1);
+        const int bits = sg.template rhs<KEEP>(s == 0, frozen, cv0, cv1, r0, r1, krec, 4 * s + 2);
         if (bits) {
             stop_bits = bits;
             return true;
@@ -135,6 +139,7 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     sg.publish(un0, un1);
     while (n < seg_end) {
         store_ckpt();
+        if (KEEP) krec = kp + (size_t)(n - st0.steps) * kRec;
         if (stage(0)) break;
 #pragma unroll 1
         for (int s = 1; s < 4; ++s) stage(s);
@@ -168,10 +173,14 @@ constexpr size_t lds_bytes_for()
 template <int P, int W>
 hipError_t launch_t(bool full, int n_blocks, const EvolveArgs& a, hipStream_t s)
 {
-    if (full)
-        evolve_kernel<P, W, true><<<dim3(n_blocks), dim3(64 * W), lds_bytes_for<P, W, true>(), s>>>(a);
-    else
-        evolve_kernel<P, W, false><<<dim3(n_blocks), dim3(64 * W), lds_bytes_for<P, W, false>(), s>>>(a);
+    const dim3 g(n_blocks), t(64 * W);
+    if (a.keep) {
+        if (full) evolve_kernel<P, W, true, true><<<g, t, lds_bytes_for<P, W, true>(), s>>>(a);
+        else evolve_kernel<P, W, false, true><<<g, t, lds_bytes_for<P, W, false>(), s>>>(a);
+    } else {
+        if (full) evolve_kernel<P, W, true, false><<<g, t, lds_bytes_for<P, W, true>(), s>>>(a);
+        else evolve_kernel<P, W, false, false><<<g, t, lds_bytes_for<P, W, false>(), s>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -180,11 +189,15 @@ hipError_t prepare_t(size_t max_lds)
 {
     const size_t nf = lds_bytes_for<P, W, true>(), np = lds_bytes_for<P, W, false>();
     if (nf > max_lds || np > max_lds) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)evolve_kernel<P, W, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)nf);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)evolve_kernel<P, W, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)np);
+    const void* kf[] = {(const void*)evolve_kernel<P, W, true, false>, (const void*)evolve_kernel<P, W, true, true>};
+    const void* kn[] = {(const void*)evolve_kernel<P, W, false, false>, (const void*)evolve_kernel<P, W, false, true>};
+    for (int i = 0; i < 2; ++i) {
+        hipError_t e = hipFuncSetAttribute(kf[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)nf);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(kn[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)np);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace

@@ -52,6 +52,10 @@ struct EvolveArgs {
     // of the segment ([slot][2][N], slot = (n - n_start) / ckpt_every)
     const double* const* src;
     double* const* ckpt;
+    // optional (the adjoint's segment recompute): per instance, the stage record
+    // of every step of the segment, [n - n_start][16][P][64 W] lane-interleaved:
+    // stage s's input (Phi, Pi), e^-delta and S in fields 4 s .. 4 s + 3
+    double* const* keep;
     int64_t total;
     double a_collapse;
     int32_t snap_every;     // > 0: stop each instance at the next multiple
@@ -187,6 +191,10 @@ struct AdjointArgs {
     const double* const* tab;
     const double* const* seg;  // per instance: U^t for t = n0..n1, [t - n0][2][N]
     double* const* stg;        // per instance: stage scratch, adjoint_scratch_len(cfg)
+    // optional: per instance, the segment's stage record written by the forward
+    // recompute (EvolveArgs::keep); the reverse then reads each step's stages
+    // from it instead of recomputing them from seg
+    double* const* keep;
     const AdjSeg* sg;          // [n_inst]
     double* Ubar;              // packed adjoint state, [2][total], updated in place
     int64_t total;
@@ -217,6 +225,8 @@ struct EndArgs {
 };
 
 size_t adjoint_scratch_len(ClassCfg c);
+// Doubles of one step's stage record (EvolveArgs::keep) in configuration c.
+size_t stage_record_len(ClassCfg c);
 hipError_t prepare_adjoint(ClassCfg c, size_t max_lds);
 hipError_t launch_adjoint(ClassCfg c, bool full, int n_blocks, const AdjointArgs& a, hipStream_t s);
 hipError_t launch_endpoint(ClassCfg c, bool full, int n_blocks, const EndArgs& a, hipStream_t s);

@@ -25,6 +25,18 @@ pytestmark = pytest.mark.gpu
 GTOL = 1e-9
 LTOL = 1e-9
 
+# The reverse sweep reads each step's stages from the record the forward
+# recompute of the segment kept, or (when the records would exceed a quarter of
+# the device memory, or with ADSCL_ADJOINT_RECOMPUTE=1) recomputes them itself.
+MODES = ["stored", "recompute"]
+
+
+def set_mode(monkeypatch, mode):
+    if mode == "recompute":
+        monkeypatch.setenv("ADSCL_ADJOINT_RECOMPUTE", "1")
+    else:
+        monkeypatch.delenv("ADSCL_ADJOINT_RECOMPUTE", raising=False)
+
 
 def relmax(g, o):
     g, o = np.asarray(g), np.asarray(o)
@@ -42,8 +54,9 @@ def run_gpu(Ns, eps, c, J, T, K, gauge=O.GAUGE_BOUNDARY, thr=0.0, n_modes=None):
     return b, L, g, v
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("gauge", [O.GAUGE_BOUNDARY, O.GAUGE_ORIGIN])
-def test_adjoint_ragged_batch_matches_oracle(gauge):
+def test_adjoint_ragged_batch_matches_oracle(monkeypatch, gauge, mode):
     """Five instances of four grid sizes (17 to 131 steps each), 8 modes in,
     drift of 4 modes, checkpoints every 7 steps.  In origin time the N=257
     instance runs unstable on both sides (its boundary speed A e^-delta grows
@@ -53,7 +66,8 @@ def test_adjoint_ragged_batch_matches_oracle(gauge):
     eps = np.array([0.5, 0.3, 0.8, 0.4, 1.0])
     Jc, J, T, K = 8, 4, 0.2, 7
     c = coeffs(11, len(Ns), Jc)
-    print("adjoint ragged gauge", gauge, flush=True)
+    set_mode(monkeypatch, mode)
+    print("adjoint ragged gauge", gauge, mode, flush=True)
     _, L, g, v = run_gpu(Ns, eps, c, J, T, K, gauge=gauge)
     n_valid = 0
     for b, N in enumerate(Ns):
@@ -67,6 +81,27 @@ def test_adjoint_ragged_batch_matches_oracle(gauge):
         e = relmax(g[b], ref["grad"])
         assert e <= GTOL, "instance %d (N=%d): gradient error %.3e" % (b, N, e)
     assert n_valid >= 4
+
+
+def test_adjoint_stored_and_recomputed_stages_agree(monkeypatch):
+    """The two ways of obtaining each step's stages in the reverse sweep (read
+    from the record of the segment's forward recompute, or recomputed by the
+    reverse kernel from the step's state) give the same gradient: the same
+    arithmetic in two compiled kernels, so equal to rounding."""
+    Ns = np.array([33, 65, 129, 257, 65, 1025], np.int32)
+    eps = np.array([0.5, 0.3, 0.8, 0.4, 1.0, 0.6])
+    c = coeffs(21, len(Ns), 8)
+    print("adjoint stored vs recomputed", flush=True)
+    out = {}
+    for mode in MODES:
+        set_mode(monkeypatch, mode)
+        _, L, g, v = run_gpu(Ns, eps, c, 4, 0.2, 7)
+        out[mode] = (L, g, v)
+    (L1, g1, v1), (L2, g2, v2) = out["stored"], out["recompute"]
+    assert np.array_equal(v1, v2) and np.all(v1 == 1)
+    assert np.max(np.abs(L1 - L2) / np.abs(L2)) <= 1e-12
+    for b in range(len(Ns)):
+        assert relmax(g1[b], g2[b]) <= 1e-12, b
 
 
 def test_adjoint_checkpoint_interval_is_bitwise_irrelevant():
@@ -226,9 +261,12 @@ TUNED_ADJ = [(257, 4, 1), (513, 4, 2), (1025, 4, 4), (2049, 4, 8), (4097, 4, 16)
              (2049, 8, 4), (1025, 16, 1), (2049, 16, 2), (4097, 16, 4), (449, 8, 1), (1901, 16, 2), (3333, 4, 16)]
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("N,P,W", TUNED_ADJ)
-def test_adjoint_every_kernel_configuration_matches_oracle(monkeypatch, N, P, W):
+def test_adjoint_every_kernel_configuration_matches_oracle(monkeypatch, N, P, W, mode):
     monkeypatch.setenv("ADSCL_TUNE", "%d:%dx%d" % (N, P, W))
+    set_mode(monkeypatch, mode)
+    print("adjoint configuration", N, P, W, mode, flush=True)
     # 120 steps of eps = 2 data: the drift E_j(t_n) - E_j(0) is at least 1e-3 of
     # E_j, so L keeps about 11 digits
     Jc, J, K = 6, 3, 9
