@@ -25,10 +25,11 @@
 namespace adscl {
 namespace {
 
-// Fields of the per-instance stage scratch, each [P][64 W]: stage s holds
-// Phi_s, Pi_s, e^-delta_s, S_s at 4 s .. 4 s + 3; then the adjoint state at the
-// start of the step's reverse (Phibar', Pibar': 16, 17) and the running adjoint
-// state (18, 19).
+// The per-instance stage scratch, in fields of [P][64 W] doubles: the first 16
+// hold a step's stage record (StageRec: Phi_s, Pi_s, e^-delta_s, S_s of the
+// four stages) when the reverse kernel recomputes the stages itself; then, as
+// LaneArr fields, the adjoint state at the start of the step's reverse
+// (Phibar', Pibar': 16, 17) and the running adjoint state (18, 19).
 constexpr int kFields = 20;
 
 template <int P, int W, bool FULL>
@@ -182,11 +183,20 @@ struct Rev {
 
     // Adjoint of one stage map V -> k = (Phi_t, Pi_t)(V): given the cotangents
     // (kb0, kb1) of k at the own points, returns (vb0, vb1) = J^T kb.  V, e^-delta
-    // and S of the stage come from the scratch fields f0 .. f0+3.
-    static __device__ __forceinline__ void stage_reverse(S_t& sg, ADSCL_GLOBAL double* stg, int f0,
+    // and S of the stage are stage si of the step's record `stg` (StageRec).
+    static __device__ __forceinline__ void stage_reverse(S_t& sg, ADSCL_GLOBAL double* stg, int si,
                                                          const double* kb0,
                                                          const double* kb1, double* vb0, double* vb1)
     {
+        // e^-delta of the stage, held through the reverse scans; loaded first,
+        // so that the record's lines (which hold the stage's other fields as
+        // well) arrive while the cotangents are exchanged
+        double VE[P];
+        {
+            const auto sv = stage_rec<P, NL>(stg, sg.tid);
+#pragma unroll
+            for (int k = 0; k < P; ++k) VE[k] = sv.ld(si, 2, k);
+        }
         const auto tb = sg.tables();
         const int tid = sg.tid, col = sg.col, N = sg.N, i0 = sg.i0;
         const double i12h = sg.i12h, kof = sg.kof;
@@ -399,14 +409,12 @@ struct Rev {
         }
 
         // stage values: e^-delta held through the reverse scans, Phi_s, Pi_s re-read
-        double Eb[P], Sb[P], VE[P];
+        double Eb[P], Sb[P];
         {
-            const auto sv = lane_arr<P, NL>(stg, tid);
-#pragma unroll
-            for (int k = 0; k < P; ++k) VE[k] = sv.ld(f0 + 2, k);
+            const auto sv = stage_rec<P, NL>(stg, tid);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const double v0 = sv.ld(f0, k), v1 = sv.ld(f0 + 1, k), E = VE[k], S = sv.ld(f0 + 3, k);
+                const double v0 = sv.ld(si, 0, k), v1 = sv.ld(si, 1, k), E = VE[k], S = sv.ld(si, 3, k);
             double f2b = sg.tab(tb, 1, k) * gb[k];
             if (tid == 0 && k == 1) f2b += 16.0 * ob;
             if (tid == 0 && k == 2) f2b -= 2.0 * ob;
@@ -421,7 +429,7 @@ struct Rev {
             }
         }
         constraint_reverse(
-            sg, [&](int f, int k) -> double { return f == 2 ? VE[k] : lane_arr<P, NL>(stg, tid).ld(f0 + f, k); }, Eb,
+            sg, [&](int f, int k) -> double { return f == 2 ? VE[k] : stage_rec<P, NL>(stg, tid).ld(si, f, k); }, Eb,
             Sb, vb0, vb1);
         if (tid == 0) vb0[0] = 0.0;  // Phi_0 is pinned
     }
@@ -497,8 +505,8 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
 #pragma unroll 1
             for (int s = 0; s < 4; ++s) {
                 double r0[P], r1[P];
-                // stores V_s, e^-delta and S of the stage to fields 4 s .. 4 s + 3
-                sg.template rhs<true>(false, false, cv0, cv1, r0, r1, stg, 4 * s + 2);
+                // stores V_s, e^-delta and S as stage s of the scratch's record
+                sg.template rhs<true>(false, false, cv0, cv1, r0, r1, stg, s);
                 if (s < 3) {
                     const double c_next = (s == 2) ? dt : 0.5 * dt;
 #pragma unroll
@@ -521,7 +529,7 @@ __global__ void __launch_bounds__(64 * W) adjoint_kernel(AdjointArgs a)
 #pragma unroll 1
         for (int s = 3; s >= 0; --s) {
             double vb0[P], vb1[P];
-            R::stage_reverse(sg, st, 4 * s, kb0, kb1, vb0, vb1);
+            R::stage_reverse(sg, st, s, kb0, kb1, vb0, vb1);
             const double cs = (s == 3) ? dt : 0.5 * dt;
             const double bp = (s == 1) ? dt / 6.0 : dt / 3.0;
 #pragma unroll

@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
     ADSCL_GLOBAL double* krec = nullptr;  // the current step's record
     auto stage = [&](const int s) -> bool {
         double r0[P], r1[P];
-        const int bits = sg.template rhs<KEEP>(s == 0, frozen, cv0, cv1, r0, r1, krec, 4 * s + 2);
+        const int bits = sg.template rhs<KEEP>(s == 0, frozen, cv0, cv1, r0, r1, krec, s);
         if (bits) {
             stop_bits = bits;
             return true;

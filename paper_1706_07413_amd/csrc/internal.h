@@ -53,8 +53,8 @@ struct EvolveArgs {
     const double* const* src;
     double* const* ckpt;
     // optional (the adjoint's segment recompute): per instance, the stage record
-    // of every step of the segment, [n - n_start][16][P][64 W] lane-interleaved:
-    // stage s's input (Phi, Pi), e^-delta and S in fields 4 s .. 4 s + 3
+    // of every step of the segment, [n - n_start][4 stages][P][64 W][4]: each RK
+    // stage's input (Phi, Pi), e^-delta and S (StageRec in stage.h)
     double* const* keep;
     int64_t total;
     double a_collapse;

@@ -160,6 +160,37 @@ __device__ __forceinline__ LaneArr<P, NL> lane_arr(ADSCL_GLOBAL double* base, in
     return LaneArr<P, NL>{(ADSCL_GLOBAL char*)base, o};
 }
 
+// One step's stage record for the adjoint: for RK stage s (0..3) and point k of
+// lane l, the stage input (Phi, Pi), e^-delta and S side by side, 32 bytes at
+// ((s P + k) 64 W + l) 32, so that a 128-byte line holds four lanes' whole
+// entries (one load brings a stage's other fields of those lanes along).  The
+// same scalar base and opaque lane offset as LaneArr.
+template <int P, int NL>
+struct StageRec {
+    ADSCL_GLOBAL char* base;
+    unsigned o;
+    __device__ __forceinline__ ADSCL_GLOBAL double* at(int s, int k) const
+    {
+        return (ADSCL_GLOBAL double*)(base + (o + (unsigned)((s * P + k) * NL * 32)));
+    }
+    __device__ __forceinline__ double ld(int s, int f, int k) const { return at(s, k)[f]; }
+    typedef double pair_t __attribute__((ext_vector_type(2)));
+    __device__ __forceinline__ void st(int s, int k, double v0, double v1, double e, double sv) const
+    {
+        ADSCL_GLOBAL pair_t* p = reinterpret_cast<ADSCL_GLOBAL pair_t*>(at(s, k));
+        p[0] = pair_t{v0, v1};
+        p[1] = pair_t{e, sv};
+    }
+};
+
+template <int P, int NL>
+__device__ __forceinline__ StageRec<P, NL> stage_rec(ADSCL_GLOBAL double* base, int lane_id)
+{
+    unsigned o = (unsigned)lane_id * 32u;
+    asm volatile("" : "+v"(o));
+    return StageRec<P, NL>{(ADSCL_GLOBAL char*)base, o};
+}
+
 // LDS of the row layout used by the chunked large-grid kernel.
 template <int P, int W>
 struct StageLayout {
@@ -566,8 +597,8 @@ struct Stage {
     // run before B3 and the function returns their workgroup-wide bits
     // (1 collapsed, 2 non-finite) without computing r when any is set.
     // r0, r1: Phi_t, Pi_t of the own points (0 at pinned points).  KEEP: also
-    // stores the stage input (v0, v1), e^-delta and S of the lane's points to
-    // fields fE - 2 .. fE + 1 of ES.
+    // stores the stage input (v0, v1), e^-delta and S of the lane's points as
+    // stage ks of the stage record ES (StageRec).
     // v0, v1: the published stage input of the own points (read on the edge
     // path, where it is not in LDS).
     // EVA (A evolved by Eq. (4), the paper's alternative to solving Eq. (5) at
@@ -578,10 +609,10 @@ struct Stage {
     // Eq. (5)).  `wout` receives w = A e^-delta of the own points.
     template <bool KEEP = false, bool EVA = false>
     __device__ __forceinline__ int rhs(bool check, bool frozen, const double* v0, const double* v1, double* r0,
-                                       double* r1, ADSCL_GLOBAL double* ES = nullptr, int fE = 0,
+                                       double* r1, ADSCL_GLOBAL double* ES = nullptr, int ks = 0,
                                        double* av = nullptr, double* wout = nullptr, bool reint = false)
     {
-        if constexpr (EDGE) return rhs_edge<KEEP, EVA>(check, frozen, v0, v1, r0, r1, ES, fE, av, wout, reint);
+        if constexpr (EDGE) return rhs_edge<KEEP, EVA>(check, frozen, v0, v1, r0, r1, ES, ks, av, wout, reint);
         __syncthreads();  // B0
         const auto tb = tables();
         double ko0[P], ko1[P], q[P];
@@ -682,14 +713,9 @@ struct Stage {
         if constexpr (KEEP) {
             // after the flux loop, so that its table loads do not wait for
             // these stores (vector loads and stores retire in issue order)
-            const auto es = lane_arr<P, NL>(ES, tid);
+            const auto es = stage_rec<P, NL>(ES, tid);
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                es.st(fE - 2, k, v0[k]);
-                es.st(fE - 1, k, v1[k]);
-                es.st(fE, k, E[k]);
-                es.st(fE + 1, k, S[k]);
-            }
+            for (int k = 0; k < P; ++k) es.st(ks, k, v0[k], v1[k], E[k], S[k]);
         }
         __syncthreads();  // B3
         if (check) {
@@ -746,7 +772,7 @@ struct Stage {
     // a stage's reads and the next stage's writes.
     template <bool KEEP, bool EVA>
     __device__ __forceinline__ int rhs_edge(bool check, bool frozen, const double* v0, const double* v1, double* r0,
-                                            double* r1, ADSCL_GLOBAL double* ES, int fE, double* av, double* wout,
+                                            double* r1, ADSCL_GLOBAL double* ES, int ks, double* av, double* wout,
                                             bool reint)
     {
         const auto tb = tables();
@@ -823,14 +849,9 @@ struct Stage {
         if constexpr (KEEP) {
             // after the flux loop, so that its table loads do not wait for
             // these stores (vector loads and stores retire in issue order)
-            const auto es = lane_arr<P, NL>(ES, tid);
+            const auto es = stage_rec<P, NL>(ES, tid);
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                es.st(fE - 2, k, v0[k]);
-                es.st(fE - 1, k, v1[k]);
-                es.st(fE, k, E[k]);
-                es.st(fE + 1, k, S[k]);
-            }
+            for (int k = 0; k < P; ++k) es.st(ks, k, v0[k], v1[k], E[k], S[k]);
         }
         __syncthreads();  // B3
         if (check) {
