@@ -68,7 +68,7 @@ struct Chunk {
     double2* F;
     double* PE;
     double* SE;
-    double* red;   // as the single-workgroup kernel, plus [4W+8, 4W+8+3G) per-chunk factors
+    double* red;   // [0,W) p totals, [W,2W) sigma totals, [2W,3W) check bits, 3W gathered bits, 4W.. p_1, p_{N-2}, 4W+7 error
     double* T;     // this chunk's coefficient tables, [3][P][NL], copied into LDS at launch
     int tid, lane, wv, g, G, a, i0, col, N;
     bool first, last, has_nm2, near_end, bgauge, frozen;
@@ -324,49 +324,43 @@ struct Chunk {
             }
             if (tid == NL - 1 && !last) rec(g)[XS_SL] = sg[P - 1];
             if (!grid_sync()) return -1;
-            // per-chunk factors F_h and the sigma carry D_g.  The records are
-            // read once, thread h reading chunk h's, so that the reads after
-            // the barrier cost one memory latency rather than one per chunk.
-            double* fac = red + 4 * W + 8;  // [0,G) F_h, [G,2G) sigma' total of h, then D_h, [2G,3G) p total of h
-            if (tid < G) {
-                const double* r = rec(tid);
-                fac[2 * G + tid] = r[XS_P];
-                fac[G + tid] = r[XS_S];
+            // per-chunk factors F_h and the sigma carry D_h: every wavefront
+            // forms them itself, lane h (< G <= 64) reading chunk h's record
+            // (so the reads after the barrier cost one memory latency) and
+            // scanning the chunk totals; its own chunk's values and the
+            // neighbours' edge values come by lane shuffles, with no LDS round
+            // trip and no workgroup barrier.  Every lane loads from its own
+            // record only (vector loads; a lane reads fields no one wrote only
+            // where its value is not used).
+            double vP = 0.0, vS = 0.0, vSF = 0.0, vSL = 0.0, vP1 = 0.0, vPN = 0.0;
+            if (lane < G) {
+                const double* r = rec(lane);
+                vP = r[XS_P];
+                vS = r[XS_S];
+                vSF = r[XS_SF];
+                vSL = r[XS_SL];
+                vP1 = r[XS_P1];
+                vPN = r[XS_PN];
             }
-            if (tid == 0) {
-                red[4 * W + 3] = rec(0)[XS_P1];
-                red[4 * W + 4] = rec(G - 1)[XS_PN];
-                if (!first && solveS) red[4 * W + 5] = rec(g - 1)[XS_SL];
-            }
-            if (tid == NL - 1 && !last && solveS) red[4 * W + 6] = rec(g + 1)[XS_SF];
-            __syncthreads();
-            if (wv == 0) {
-                // lane h (< G <= 64) for chunk h: the p carry C_h and grid total
-                // by a wavefront scan, F_h, then the sigma carry D_h = sum over
-                // c < h of F_c (sigma' total of c) by a second scan
-                const double p1 = red[4 * W + 3];
-                const double v = (lane < G) ? fac[2 * G + lane] : 0.0;
-                const double inc = wave_incl_scan(v);
-                const double tp = __shfl(inc, 63);
-                const double Cg = inc - v;
-                const double dNg = -h24 * (24.0 * tp + 2.0 * red[4 * W + 4] + 2.0 * p1);
-                const double shift = bgauge ? dNg : 0.0;
-                const double Fh = exp(24.0 * h24 * Cg + 2.0 * h24 * p1 + shift);
-                const double fs = (lane < G) ? Fh * fac[G + lane] : 0.0;
-                const double inc2 = wave_incl_scan(fs);
-                if (lane < G) {
-                    fac[lane] = Fh;
-                    fac[G + lane] = inc2 - fs;
-                }
-                if (lane == 0) red[4 * W + 2] = dNg;
-            }
-            __syncthreads();
-            const double Fg = fac[g];
-            const double Dg = fac[G + g];
+            const double p1 = __shfl(vP1, 0);
+            const double pN2 = __shfl(vPN, G - 1);
+            const double inc = wave_incl_scan(vP);
+            const double tp = __shfl(inc, 63);
+            const double dNg = -h24 * (24.0 * tp + 2.0 * pN2 + 2.0 * p1);
+            const double shift = bgauge ? dNg : 0.0;
+            const double Fh = exp(24.0 * h24 * (inc - vP) + 2.0 * h24 * p1 + shift);
+            const double fs = (lane < G) ? Fh * vS : 0.0;
+            const double Dh = wave_incl_scan(fs) - fs;
+            const double Fg = __shfl(Fh, g);
+            const double Dg = __shfl(Dh, g);
+            const double Fl = __shfl(Fh, first ? g : g - 1);
+            const double Fr = __shfl(Fh, last ? g : g + 1);
+            const double eL = __shfl(vSL, first ? g : g - 1);  // sigma' at the last point of chunk g - 1
+            const double eR = __shfl(vSF, last ? g : g + 1);   // sigma' at the first point of chunk g + 1
             const double sl = !solveS ? 0.0 : (tid > 0) ? SE[NL + tid - 1]
-                                        : (first ? sg[1] : red[4 * W + 5] * fac[g - 1] / Fg);
+                                        : (first ? sg[1] : eL * Fl / Fg);
             const double sr = !solveS ? 0.0 : (tid < NL - 1) ? SE[tid + 1]
-                                        : (last ? 0.0 : red[4 * W + 6] * fac[g + 1] / Fg);
+                                        : (last ? 0.0 : eR * Fr / Fg);
             {
                 double R2 = carry2;
 #pragma unroll
@@ -378,7 +372,7 @@ struct Chunk {
                     E[k] *= Fg;
                 }
             }
-            dN = red[4 * W + 2];
+            dN = dNg;
         }
 
         // fluxes
@@ -511,11 +505,11 @@ struct Chunk {
     }
 };
 
-// LDS of a chunk: rows, sigma edges, reductions, per-chunk factors, tables
+// LDS of a chunk: rows, sigma edges, reductions, tables
 template <int P, int W>
 constexpr size_t big_lds_bytes_for()
 {
-    return (StageLayout<P, W>::lds_doubles + (size_t)3 * kBigMaxChunks + (size_t)3 * P * 64 * W) * sizeof(double);
+    return (StageLayout<P, W>::lds_doubles + (size_t)3 * P * 64 * W) * sizeof(double);
 }
 
 // RK: Runge-Kutta order (4 classical; 3 and 2 the Shu-Osher methods, as the
@@ -566,7 +560,7 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.tabL = (!cs.first && cs.tid == 0) ? cs.tab_at(0, cs.a - 1) : 0.0;
     cs.tabR = (!cs.last && cs.tid == Ch::NL - 1) ? cs.tab_at(0, cs.a + Ch::C) : 0.0;
     // each lane copies exactly the table entries it reads later: no barrier
-    cs.T = cs.red + 4 * W + 8 + 3 * kBigMaxChunks;
+    cs.T = cs.red + 4 * W + 8;
 #pragma unroll
     for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
     cs.xg = x.xch + (size_t)bd.first * XREC;
@@ -812,7 +806,7 @@ bool big_class_supported(ClassCfg c)
 
 size_t big_lds_bytes(ClassCfg c)
 {
-    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * kBigMaxChunks + 3 * c.P * 64 * c.W) *
+    return ((size_t)4 * c.P * (64 * c.W + 2) + 2 * 64 * c.W + 4 * c.W + 8 + 3 * c.P * 64 * c.W) *
            sizeof(double);
 }
 

@@ -117,8 +117,8 @@ hipError_t big_capacity(ClassCfg c, int rk, bool eva, int device, int* blocks);
 // configuration c, sum of their chunks = blocks <= big_capacity).
 hipError_t launch_evolve_big(ClassCfg c, int rk, bool eva, int blocks, const EvolveArgs& a, const BigArgs& x,
                              hipStream_t s);
-// At most 64 chunks: the kernel keeps three per-chunk factors in 3 * 64 LDS
-// slots and gathers the chunks' collapse bits with one wavefront.
+// At most 64 chunks: the kernel scans the chunks' totals and gathers their
+// collapse bits with one wavefront lane per chunk.
 constexpr int kBigMaxChunks = 64;
 // 64-bit words between two instances' barrier counters: one 256-byte block
 // each, so that the instances of a launch do not poll and count on one line.
