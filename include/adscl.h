@@ -234,12 +234,17 @@ int adscl_sync(adscl_ctx* ctx);
 
 /* Launch plan of the fused evolution kernel.  Instances are grouped into
  * classes that share a kernel configuration (P grid points per lane, W
- * wavefronts per instance); each class is one launch on its own stream.
+ * wavefronts per instance); each class is one launch on its own stream.  When
+ * the environment sets ADSCL_PAIR=1 at adscl_create and the scheme is classical
+ * RK4, a class of full (8, 8) instances (N = 4097) also runs the instances of a
+ * full (8, 4) class (N = 2049) in its launch, two per workgroup after its own.
  * Host outputs (any may be NULL): n_classes; per class (up to max_classes):
  * P, W, number of member instances, and the duration in ms of its launch in
  * the last adscl_step call (measured with HIP events on the class's stream when
- * the context was created with ADSCL_TIME_KERNELS, else -1); cls [n_inst]: the
- * class of each instance.  Synchronises the context's stream. */
+ * the context was created with ADSCL_TIME_KERNELS, else -1; -1 also for a
+ * class whose instances ran in another class's launch); cls [n_inst]: the
+ * class whose launch advances each instance in adscl_step (its own class, or
+ * the class that runs it in pairs).  Synchronises the context's stream. */
 int adscl_kernel_stats(adscl_ctx* ctx, int32_t max_classes, int32_t* n_classes, int32_t* P, int32_t* W,
                        int32_t* members, double* last_ms, int32_t* cls);
 

@@ -38,6 +38,13 @@ struct LaunchClass {
     bool timed = false;
     // one large instance over `chunks` workgroups (0: one workgroup per instance)
     int chunks = 0;
+    // forward pass only: the class whose instances this class's launch also
+    // runs, two per workgroup (-1: none), and its launch order (this class's
+    // instances, then that class's); or, for that class, the class whose launch
+    // runs its instances (-1: its own launch)
+    int pair = -1;
+    int32_t* d_order_pair = nullptr;
+    int host = -1;
 };
 
 // One cooperative launch of the multi-workgroup kernel over several large
@@ -406,13 +413,24 @@ int run_evolve(adscl_ctx* c, const EvolveArgs& base, bool timing = true)
             }
         }
     }
+    const bool pairs = base.keep == nullptr;  // the pair kernel writes no stage records
     return run_classes(c, [&](LaunchClass& lc, hipStream_t s) -> hipError_t {
+        if (pairs && lc.host >= 0) {  // runs in its host class's launch
+            lc.timed = false;
+            return hipSuccess;
+        }
         EvolveArgs a = base;
         a.order = lc.d_order;
         hipError_t e = hipSuccess;
         if (timing && lc.t0 && (e = hipEventRecord(lc.t0, s)) != hipSuccess) return e;
-        e = scheme(c) ? launch_evolve_scheme(lc.cfg, c->rk, c->a_reint > 0, lc.full, (int)lc.inst.size(), a, s)
-                      : launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s);
+        if (pairs && lc.pair >= 0) {
+            a.order = lc.d_order_pair;
+            const int ns = (int)lc.inst.size();
+            e = launch_evolve_pair(lc.cfg, ns, ns + (int)c->classes[lc.pair].inst.size(), a, s);
+        } else {
+            e = scheme(c) ? launch_evolve_scheme(lc.cfg, c->rk, c->a_reint > 0, lc.full, (int)lc.inst.size(), a, s)
+                          : launch_evolve(lc.cfg, lc.full, (int)lc.inst.size(), a, s);
+        }
         if (e != hipSuccess) return e;
         if (timing && lc.t1) {
             if ((e = hipEventRecord(lc.t1, s)) != hipSuccess) return e;
@@ -1035,6 +1053,33 @@ int adscl_create(const adscl_config* cfg, void* hip_stream, adscl_ctx** out)
     });
     c->n_big = 0;
     for (const LaunchClass& lc : c->classes) c->n_big += lc.chunks > 0;
+    // Pair launches (plain RK4 only; after the sort, which fixes the class
+    // indices that `pair` and `host` hold): a full (P, W) class also runs a full
+    // (P, W/2) class's instances two per workgroup in its own launch, after its
+    // own instances in dispatch order, so that they start on the compute units
+    // its instances free instead of after its whole launch.  Opt-in
+    // (ADSCL_PAIR=1): on the 1024-instance Gaussian workload the pass took
+    // longer this way than with every class in a launch of its own.
+    const char* pair_env = std::getenv("ADSCL_PAIR");
+    if (!scheme(c) && pair_env && std::strcmp(pair_env, "1") == 0) {
+        for (int x = 0; x < (int)c->classes.size(); ++x) {
+            LaunchClass& X = c->classes[x];
+            if (X.chunks || !X.full || X.host >= 0 || !pair_supported(X.cfg)) continue;
+            for (int y = 0; y < (int)c->classes.size(); ++y) {
+                LaunchClass& Y = c->classes[y];
+                if (y == x || Y.chunks || !Y.full || Y.pair >= 0 || Y.host >= 0) continue;
+                if (Y.cfg.P != X.cfg.P || 2 * Y.cfg.W != X.cfg.W) continue;
+                TRY_C(prepare_evolve_pair(X.cfg, c->max_lds));
+                std::vector<int32_t> ord = X.inst;
+                ord.insert(ord.end(), Y.inst.begin(), Y.inst.end());
+                TRY_C(hipMalloc((void**)&X.d_order_pair, ord.size() * sizeof(int32_t)));
+                TRY_C(hipMemcpy(X.d_order_pair, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                X.pair = y;
+                Y.host = x;
+                break;
+            }
+        }
+    }
     // large instances: one cooperative launch per configuration, split where
     // the device cannot hold all their workgroups at once
     for (int k = 0; k < (int)c->classes.size(); ++k) {
@@ -1121,6 +1166,7 @@ void adscl_destroy(adscl_ctx* c)
     }
     for (LaunchClass& lc : c->classes) {
         if (lc.d_order) (void)hipFree(lc.d_order);
+        if (lc.d_order_pair) (void)hipFree(lc.d_order_pair);
         if (lc.stream) (void)hipStreamDestroy(lc.stream);
         if (lc.done) (void)hipEventDestroy(lc.done);
         if (lc.t0) (void)hipEventDestroy(lc.t0);
@@ -1486,7 +1532,7 @@ int adscl_kernel_stats(adscl_ctx* c, int32_t max_classes, int32_t* n_classes, in
             last_ms[k] = ms;
         }
         if (cls)
-            for (int32_t b : lc.inst) cls[b] = k;
+            for (int32_t b : lc.inst) cls[b] = lc.host >= 0 ? lc.host : k;
     }
     return ADSCL_OK;
 }

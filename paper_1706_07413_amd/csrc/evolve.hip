@@ -27,6 +27,8 @@
 //
 // The stage machinery (LDS layout, parity ghosts, the two scans, fluxes)
 // lives in stage.h, shared with the adjoint kernel's forward recomputation.
+// evolve_pair_kernel (opt-in) runs the instances of a (P, W/2) class two per
+// workgroup inside a (P, W) class's launch.
 #include <algorithm>
 
 #include "stage.h"
@@ -34,49 +36,71 @@
 namespace adscl {
 namespace {
 
+// The evolution of one instance by W wavefronts: its state in registers, its
+// Stage over the LDS at `lds`, t the thread's index within the instance.
 // KEEP: also writes the stage record of every step (EvolveArgs::keep).
 template <int P, int W, bool FULL, bool KEEP>
-__global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
-{
-    extern __shared__ double lds[];
-    const int b = a.order[blockIdx.x];
-    const InstStatus st0 = a.status[b];
-    if (st0.state == ST_COLLAPSED || st0.state == ST_NONFINITE) return;
-
-    const InstConst ic = a.ic[b];
-    const int64_t off = ic.off;
-    const bool frozen = a.frozen != 0;
+struct Run {
+    static constexpr size_t kRec = (size_t)16 * P * 64 * W;  // doubles of one step's stage record
     Stage<P, W, FULL, true> sg;
-    sg.setup(lds, ic, a.tab[b], a.gauge, a.a_collapse);
-    const int N = sg.N, i0 = sg.i0;
-    const double dt = sg.dt;
-
     double un0[P], un1[P], acc0[P], acc1[P], cv0[P], cv1[P];  // cv: the current stage input
-    const ADSCL_GLOBAL double* s0 = gmem(a.Phi + off);
-    const ADSCL_GLOBAL double* s1 = gmem(a.Pi + off);
-    if (a.src) {
-        s0 = gmem(a.src[b]) + (size_t)(st0.steps / a.src_every) * 2 * (size_t)N;
-        s1 = s0 + N;
-    }
+    InstStatus st0;
+    int64_t off, n, seg_end;
+    double dt;
+    int stop_bits;
+    bool frozen;
+    ADSCL_GLOBAL double* ck;    // checkpoints of the segment, or null
+    ADSCL_GLOBAL double* kp;    // KEEP: the segment's stage records
+    ADSCL_GLOBAL double* krec;  // KEEP: the current step's record
+
+    // Loads instance b; false when it has already stopped (nothing to run).
+    __device__ __forceinline__ bool init(const EvolveArgs& a, int b, double* lds, int t)
+    {
+        st0 = a.status[b];
+        if (st0.state == ST_COLLAPSED || st0.state == ST_NONFINITE) return false;
+        const InstConst ic = a.ic[b];
+        off = ic.off;
+        frozen = a.frozen != 0;
+        sg.setup(lds, ic, a.tab[b], a.gauge, a.a_collapse, t);
+        const int N = sg.N, i0 = sg.i0;
+        dt = sg.dt;
+        const ADSCL_GLOBAL double* s0 = gmem(a.Phi + off);
+        const ADSCL_GLOBAL double* s1 = gmem(a.Pi + off);
+        if (a.src) {
+            s0 = gmem(a.src[b]) + (size_t)(st0.steps / a.src_every) * 2 * (size_t)N;
+            s1 = s0 + N;
+        }
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const int j = i0 + k;
-        const bool o = sg.own(k);
-        un0[k] = o ? s0[j] : 0.0;
-        un1[k] = o ? s1[j] : 0.0;
-        acc0[k] = 0.0;
-        acc1[k] = 0.0;
-        cv0[k] = un0[k];
-        cv1[k] = un1[k];
+        for (int k = 0; k < P; ++k) {
+            const int j = i0 + k;
+            const bool o = sg.own(k);
+            un0[k] = o ? s0[j] : 0.0;
+            un1[k] = o ? s1[j] : 0.0;
+            acc0[k] = 0.0;
+            acc1[k] = 0.0;
+            cv0[k] = un0[k];
+            cv1[k] = un1[k];
+        }
+        stop_bits = 0;
+        kp = KEEP ? gmem(a.keep[b]) : nullptr;
+        krec = nullptr;
+        // Advance to the end of this segment: the call's target step, or the
+        // next snapshot step when snapshots are on.
+        n = st0.steps;
+        seg_end = st0.target;
+        if (a.snap_every > 0) {
+            const int64_t nb = (n / a.snap_every + 1) * a.snap_every;
+            if (nb < seg_end) seg_end = nb;
+        }
+        // checkpoints of the segment: U^n for n - n_start a multiple of ckpt_every
+        ck = (a.ckpt && a.ckpt_every > 0) ? gmem(a.ckpt[b]) : nullptr;
+        return true;
     }
 
     // One RK4 stage on the published stage input; returns true when stage 0
     // finds the instance collapsed or non-finite (nothing is updated then).
-    int stop_bits = 0;
-    constexpr size_t kRec = (size_t)16 * P * 64 * W;  // doubles of one step's stage record
-    ADSCL_GLOBAL double* const kp = KEEP ? gmem(a.keep[b]) : nullptr;
-    ADSCL_GLOBAL double* krec = nullptr;  // the current step's record
-    auto stage = [&](const int s) -> bool {
+    __device__ __forceinline__ bool stage(const int s)
+    {
         double r0[P], r1[P];
         const int bits = sg.template rhs<KEEP>(s == 0, frozen, cv0, cv1, r0, r1, krec, s);
         if (bits) {
@@ -107,21 +131,14 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
         // every lane read U_s before B3, so U_{s+1} may replace it now
         sg.publish(cv0, cv1);
         return false;
-    };
-
-    // Advance to the end of this segment: the call's target step, or the next
-    // snapshot step when snapshots are on.
-    int64_t n = st0.steps;
-    int64_t seg_end = st0.target;
-    if (a.snap_every > 0) {
-        const int64_t nb = (n / a.snap_every + 1) * a.snap_every;
-        if (nb < seg_end) seg_end = nb;
     }
-    // checkpoints of the segment: U^n for n - n_start a multiple of ckpt_every
-    ADSCL_GLOBAL double* const ck = (a.ckpt && a.ckpt_every > 0) ? gmem(a.ckpt[b]) : nullptr;
-    auto store_ckpt = [&]() {
+
+    // Start of step n: the checkpoint due at n, the step's stage record.
+    __device__ __forceinline__ void begin_step(const EvolveArgs& a)
+    {
         const int64_t r = n - st0.steps;
         if (ck && r % a.ckpt_every == 0) {
+            const int N = sg.N, i0 = sg.i0;
             ADSCL_GLOBAL double* d = ck + (size_t)(r / a.ckpt_every) * 2 * (size_t)N;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
@@ -135,33 +152,125 @@ __global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
                 d[2 * N - 1] = 0.0;
             }
         }
-    };
-    sg.publish(un0, un1);
-    while (n < seg_end) {
-        store_ckpt();
         if (KEEP) krec = kp + (size_t)(n - st0.steps) * kRec;
-        if (stage(0)) break;
-#pragma unroll 1
-        for (int s = 1; s < 4; ++s) stage(s);
-        ++n;
     }
-    if (n == seg_end) store_ckpt();
+
+    // End of the segment: the last checkpoint, the state and the status (thread
+    // t == 0 writes the status).
+    __device__ __forceinline__ void finish(const EvolveArgs& a, int b, int t)
+    {
+        if (n == seg_end && ck) begin_step(a);
+        const int i0 = sg.i0;
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        if (sg.own(k)) {
-            a.Phi[off + i0 + k] = un0[k];
-            a.Pi[off + i0 + k] = un1[k];
+        for (int k = 0; k < P; ++k) {
+            if (sg.own(k)) {
+                a.Phi[off + i0 + k] = un0[k];
+                a.Pi[off + i0 + k] = un1[k];
+            }
+        }
+        if (t == 0) {
+            InstStatus o = st0;
+            o.steps = n;
+            if (stop_bits) {
+                o.state = (stop_bits & 2) ? ST_NONFINITE : ST_COLLAPSED;
+                o.t_c = (double)n * dt;
+            }
+            a.status[b] = o;
         }
     }
-    if (threadIdx.x == 0) {
-        InstStatus o = st0;
-        o.steps = n;
-        if (stop_bits) {
-            o.state = (stop_bits & 2) ? ST_NONFINITE : ST_COLLAPSED;
-            o.t_c = (double)n * dt;
-        }
-        a.status[b] = o;
+};
+
+template <int P, int W, bool FULL, bool KEEP>
+__device__ __forceinline__ void evolve_one(const EvolveArgs& a, int b, double* lds)
+{
+    Run<P, W, FULL, KEEP> r;
+    if (!r.init(a, b, lds, threadIdx.x)) return;
+    r.sg.publish(r.un0, r.un1);
+    while (r.n < r.seg_end) {
+        r.begin_step(a);
+        if (r.stage(0)) break;
+#pragma unroll 1
+        for (int s = 1; s < 4; ++s) r.stage(s);
+        ++r.n;
     }
+    r.finish(a, b, threadIdx.x);
+}
+
+template <int P, int W, bool FULL, bool KEEP>
+__global__ void __launch_bounds__(64 * W) evolve_kernel(EvolveArgs a)
+{
+    extern __shared__ double lds[];
+    evolve_one<P, W, FULL, KEEP>(a, a.order[blockIdx.x], lds);
+}
+
+// LDS doubles of one half of a pair workgroup (even, so that the second half's
+// double2 slots stay 16-byte aligned).
+template <int P, int WH>
+constexpr size_t pair_half_doubles()
+{
+    return (Stage<P, WH, true, true>::lds_doubles + 1) & ~(size_t)1;
+}
+
+// One launch of a full (P, W) class whose workgroups past the first n_single
+// each run two instances of a full (P, W/2) class side by side: order[0,
+// n_single) are the (P, W) instances, order[n_single, n_inst) the (P, W/2)
+// ones, taken two per workgroup.  Each half keeps its own Stage over its own
+// LDS; the halves share only the workgroup barriers, so they step in
+// lock-step, and a half whose instance has stopped (or that has none) passes
+// the same barriers without computing until both have stopped.  Placed in the
+// dispatch order after the (P, W) instances, the pairs take the compute units
+// those free as they end, instead of waiting for the whole (P, W) launch.
+template <int P, int W>
+__global__ void __launch_bounds__(64 * W) evolve_pair_kernel(EvolveArgs a, int n_single, int n_inst)
+{
+    extern __shared__ double lds[];
+    if ((int)blockIdx.x < n_single) {
+        evolve_one<P, W, true, false>(a, a.order[blockIdx.x], lds);
+        return;
+    }
+    constexpr int WH = W / 2;
+    constexpr size_t HL = pair_half_doubles<P, WH>();
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / (64 * WH));  // uniform per wavefront
+    const int t = (int)threadIdx.x - half * 64 * WH;
+    volatile int* const act = reinterpret_cast<volatile int*>(lds + 2 * HL);  // [2]: half running this step
+    const int slot = n_single + 2 * ((int)blockIdx.x - n_single) + half;
+    const int b = slot < n_inst ? a.order[slot] : -1;
+    Run<P, WH, true, false> r;
+    // `loaded`, `run` and the exit test are uniform over each half (readfirstlane
+    // makes that visible to the compiler), so the branches below are jumps of
+    // whole wavefronts and no wavefront passes a barrier of the branch it skips
+    const bool loaded = __builtin_amdgcn_readfirstlane((b >= 0) && r.init(a, b, lds + half * HL, t)) != 0;
+    bool run = loaded;
+    // a stage of Stage::rhs on the edge path passes this many barriers
+    const int nbar = Stage<P, WH, true, true>::edge_barriers(a.frozen != 0);
+    auto idle = [&]() {
+#pragma unroll 1
+        for (int i = 0; i < nbar; ++i) __syncthreads();
+    };
+    if (run) r.sg.publish(r.un0, r.un1);
+    for (;;) {
+        if (run && r.n >= r.seg_end) run = false;
+        run = __builtin_amdgcn_readfirstlane(run) != 0;
+        // written before this step's first barrier, read after it; the next
+        // write follows the barriers of stages 1-3
+        if (t == 0) act[half] = run ? 1 : 0;
+        if (run) {
+            r.begin_step(a);
+            if (r.stage(0)) run = false;
+        } else {
+            idle();
+        }
+        run = __builtin_amdgcn_readfirstlane(run) != 0;
+        // both halves leave after the same stage, on the same two flags
+        if (__builtin_amdgcn_readfirstlane(act[0] | act[1]) == 0) break;
+#pragma unroll 1
+        for (int s = 1; s < 4; ++s) {
+            if (run) r.stage(s);
+            else idle();
+        }
+        if (run) ++r.n;
+    }
+    if (loaded) r.finish(a, b, t);
 }
 
 template <int P, int W, bool FULL>
@@ -198,6 +307,12 @@ hipError_t prepare_t(size_t max_lds)
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int P, int W>
+constexpr size_t pair_lds_bytes()
+{
+    return std::max(lds_bytes_for<P, W, true>(), (2 * pair_half_doubles<P, W / 2>() + 2) * sizeof(double));
 }
 
 }  // namespace
@@ -250,6 +365,47 @@ hipError_t launch_evolve(ClassCfg c, bool full, int n_blocks, const EvolveArgs& 
 #define X(p, w) \
     if (c.P == p && c.W == w) return launch_t<p, w>(full, n_blocks, a, s);
     ADSCL_CLASSES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// Pair launches (evolve_pair_kernel): the (P, W) configurations whose launch
+// can also run (P, W/2) instances two per workgroup.
+#define ADSCL_PAIR_CLASSES(X) X(8, 8)
+
+bool pair_supported(ClassCfg c)
+{
+#define X(p, w) \
+    if (c.P == p && c.W == w) return true;
+    ADSCL_PAIR_CLASSES(X)
+#undef X
+    return false;
+}
+
+hipError_t prepare_evolve_pair(ClassCfg c, size_t max_lds)
+{
+#define X(p, w)                                                                                            \
+    if (c.P == p && c.W == w) {                                                                           \
+        if (pair_lds_bytes<p, w>() > max_lds) return hipErrorInvalidValue;                                 \
+        return hipFuncSetAttribute((const void*)evolve_pair_kernel<p, w>,                                 \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)pair_lds_bytes<p, w>()); \
+    }
+    ADSCL_PAIR_CLASSES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_evolve_pair(ClassCfg c, int n_single, int n_inst, const EvolveArgs& a, hipStream_t s)
+{
+    if (n_single < 0 || n_inst < n_single) return hipErrorInvalidValue;
+    const int blocks = n_single + (n_inst - n_single + 1) / 2;
+    if (blocks == 0) return hipSuccess;
+#define X(p, w)                                                                                                   \
+    if (c.P == p && c.W == w) {                                                                                  \
+        evolve_pair_kernel<p, w><<<dim3(blocks), dim3(64 * w), pair_lds_bytes<p, w>(), s>>>(a, n_single, n_inst); \
+        return hipGetLastError();                                                                                \
+    }
+    ADSCL_PAIR_CLASSES(X)
 #undef X
     return hipErrorInvalidValue;
 }

@@ -81,6 +81,12 @@ size_t evolve_lds_bytes(ClassCfg c);
 hipError_t prepare_evolve(ClassCfg c, size_t max_lds);
 // full: every instance of the launch has N - 1 == 64 W P.
 hipError_t launch_evolve(ClassCfg c, bool full, int n_blocks, const EvolveArgs& a, hipStream_t s);
+// Pair launch of a full (P, W) class: a.order[0, n_single) are its instances
+// (one workgroup each), a.order[n_single, n_inst) instances of a full
+// (P, W/2) class, two per workgroup, in the same launch.
+bool pair_supported(ClassCfg c);
+hipError_t prepare_evolve_pair(ClassCfg c, size_t max_lds);
+hipError_t launch_evolve_pair(ClassCfg c, int n_single, int n_inst, const EvolveArgs& a, hipStream_t s);
 // The scheme variants (scheme.hip): RK order 2 or 3 (A solved or evolved), or
 // 4 with A evolved (eva), on the configurations scheme_class_supported accepts.
 bool scheme_class_supported(ClassCfg c);

@@ -257,6 +257,14 @@ struct Stage {
     __device__ __forceinline__ void setup(double* lds, const InstConst& ic, const double* tab, int gauge,
                                           double a_collapse)
     {
+        setup(lds, ic, tab, gauge, a_collapse, (int)threadIdx.x);
+    }
+
+    // t: the thread's index within the 64 W threads that run the instance (the
+    // workgroup's own index unless the workgroup runs several instances).
+    __device__ __forceinline__ void setup(double* lds, const InstConst& ic, const double* tab, int gauge,
+                                          double a_collapse, int t)
+    {
         double* p = lds;
         U = F = XU = XF = RU = nullptr;
         PE = SE = XP = XS = T = RF = RSb = RDt = nullptr;
@@ -296,7 +304,7 @@ struct Stage {
         red = p;
         X64 = red + 4 * W + 8;
         buf = 0;
-        tid = threadIdx.x;
+        tid = t;
         // read only after the barrier of the first constraint solve
         if (tid < 64) X64[tid] = exp2((double)tid * (1.0 / 64.0));
         lane = tid & 63;
@@ -770,6 +778,10 @@ struct Stage {
     // with the metric frozen, when B3 is a stage's only barrier; the scan slots
     // (XP, XS) are written before B1 / B2 and read after them, with B3 between
     // a stage's reads and the next stage's writes.
+    // Barriers one call of rhs_edge passes (EVA off): B1, B2 and B3, or B3
+    // alone with the metric frozen.
+    static __device__ __forceinline__ int edge_barriers(bool frozen) { return frozen ? 1 : 3; }
+
     template <bool KEEP, bool EVA>
     __device__ __forceinline__ int rhs_edge(bool check, bool frozen, const double* v0, const double* v1, double* r0,
                                             double* r1, ADSCL_GLOBAL double* ES, int ks, double* av, double* wout,
