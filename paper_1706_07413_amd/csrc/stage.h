@@ -490,6 +490,9 @@ struct Stage {
         }
         dN = -h24 * (24.0 * tot + 2.0 * pN2 + 2.0 * p1);        // delta~_{N-1}
         const double shift = bgauge ? dN : 0.0;
+        // -delta = h24 (24 R - 12 p + p_m - p_p + 2 p_1) + shift, with h24
+        // distributed over the terms: one add and three FMAs per point
+        const double a24 = 24.0 * h24, a12 = -12.0 * h24, c0 = fma(2.0 * h24, p1, shift);
 
         double sg[P];
         double R = carry, stot = 0.0;
@@ -498,9 +501,9 @@ struct Stage {
             R += p[k];
             const double pm = (k == 0) ? pl : p[k - 1];
             const double pp = (k == P - 1) ? pr : p[k + 1];
-            const double dtil = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp + 2.0 * p1);
-            dl[k] = dtil - shift;
-            E[k] = exp_tab(-dl[k], X64);
+            const double nd = fma(a24, R, fma(a12, p[k], fma(h24, pm - pp, c0)));
+            dl[k] = -nd;
+            E[k] = exp_tab(nd, X64);
             sg[k] = tab(tb, 1, k) * q[k] * E[k];  // table is 0 off 1..N-2
             stot += sg[k];
         }
@@ -533,7 +536,8 @@ struct Stage {
             R2 += sg[k];
             const double sm = (k == 0) ? sl : sg[k - 1];
             const double sp = (k == P - 1) ? sr : sg[k + 1];
-            S[k] = h24 * (24.0 * R2 - 12.0 * sg[k] + sm - sp);
+            // h24 (24 R2 - 12 sigma + sigma_m - sigma_p), h24 distributed
+            S[k] = fma(a24, R2, fma(a12, sg[k], h24 * (sm - sp)));
         }
     }
 
@@ -585,15 +589,16 @@ struct Stage {
         }
         dN = -h24 * (24.0 * tot + 2.0 * pN2 + 2.0 * p1);
         const double shift = bgauge ? dN : 0.0;
+        const double a24 = 24.0 * h24, a12 = -12.0 * h24, c0 = fma(2.0 * h24, p1, shift);
         double R = carry;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             R += p[k];
             const double pm = (k == 0) ? pl : p[k - 1];
             const double pp = (k == P - 1) ? pr : p[k + 1];
-            const double dtil = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp + 2.0 * p1);
-            dl[k] = dtil - shift;
-            E[k] = exp_tab(-dl[k], X64);
+            const double nd = fma(a24, R, fma(a12, p[k], fma(h24, pm - pp, c0)));  // -delta, as in constraints
+            dl[k] = -nd;
+            E[k] = exp_tab(nd, X64);
         }
     }
 
