@@ -70,6 +70,7 @@ struct Chunk {
     double* SE;
     double* red;   // [0,W) p totals, [W,2W) sigma totals, [2W,3W) check bits, 3W gathered bits, 4W.. p_1, p_{N-2}, 4W+7 error
     double* T;     // this chunk's coefficient tables, [3][P][NL], copied into LDS at launch
+    double* X64;   // 2^(j/64), j = 0..63, the table of exp_tab
     int tid, lane, wv, g, G, a, i0, col, N;
     bool first, last, has_nm2, near_end, bgauge, frozen;
     double h24, i12h, kof, thr;
@@ -286,15 +287,16 @@ struct Chunk {
                 const double2 u = U[NL + 1];  // point a + C
                 pr = tabR * (u.x * u.x + u.y * u.y);
             }
-            double sg[P], dp[P];
+            double sg[P];
             double R = carry, stot = 0.0;
+            const double a24 = 24.0 * h24, a12 = -12.0 * h24;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 R += p[k];
                 const double pm = (k == 0) ? pl : p[k - 1];
                 const double pp = (k == P - 1) ? pr : p[k + 1];
-                dp[k] = -h24 * (24.0 * R - 12.0 * p[k] + pm - pp);
-                E[k] = exp(-dp[k]);
+                // minus the chunk-local delta~': h24 (24 R - 12 p + p_m - p_p), h24 distributed
+                E[k] = exp_tab(fma(a24, R, fma(a12, p[k], h24 * (pm - pp))), X64);
                 sg[k] = solveS ? tab(tb, 1, k) * q[k] * E[k] : 0.0;
                 stot += sg[k];
             }
@@ -348,7 +350,7 @@ struct Chunk {
             const double tp = __shfl(inc, 63);
             const double dNg = -h24 * (24.0 * tp + 2.0 * pN2 + 2.0 * p1);
             const double shift = bgauge ? dNg : 0.0;
-            const double Fh = exp(24.0 * h24 * (inc - vP) + 2.0 * h24 * p1 + shift);
+            const double Fh = exp_tab(fma(24.0 * h24, inc - vP, fma(2.0 * h24, p1, shift)), X64);
             const double fs = (lane < G) ? Fh * vS : 0.0;
             const double Dh = wave_incl_scan(fs) - fs;
             const double Fg = __shfl(Fh, g);
@@ -362,13 +364,15 @@ struct Chunk {
             const double sr = !solveS ? 0.0 : (tid < NL - 1) ? SE[tid + 1]
                                         : (last ? 0.0 : eR * Fr / Fg);
             {
+                const double aF = 24.0 * h24 * Fg, hF = h24 * Fg, aD = 24.0 * h24 * Dg;
                 double R2 = carry2;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     R2 += sg[k];
                     const double sm = (k == 0) ? sl : sg[k - 1];
                     const double sp = (k == P - 1) ? sr : sg[k + 1];
-                    S[k] = h24 * (24.0 * (Dg + Fg * R2) + Fg * (-12.0 * sg[k] + sm - sp));
+                    // h24 (24 (Dg + Fg R2) + Fg (-12 sigma + sigma_m - sigma_p)), h24 and Fg distributed
+                    S[k] = fma(aF, R2, fma(hF, fma(-12.0, sg[k], sm - sp), aD));
                     E[k] *= Fg;
                 }
             }
@@ -509,7 +513,7 @@ struct Chunk {
 template <int P, int W>
 constexpr size_t big_lds_bytes_for()
 {
-    return (StageLayout<P, W>::lds_doubles + (size_t)3 * P * 64 * W) * sizeof(double);
+    return (StageLayout<P, W>::lds_doubles + (size_t)3 * P * 64 * W + 64) * sizeof(double);
 }
 
 // RK: Runge-Kutta order (4 classical; 3 and 2 the Shu-Osher methods, as the
@@ -561,6 +565,9 @@ __global__ void __launch_bounds__(64 * W) evolve_big_kernel(EvolveArgs a, BigArg
     cs.tabR = (!cs.last && cs.tid == Ch::NL - 1) ? cs.tab_at(0, cs.a + Ch::C) : 0.0;
     // each lane copies exactly the table entries it reads later: no barrier
     cs.T = cs.red + 4 * W + 8;
+    cs.X64 = cs.T + 3 * P * Ch::NL;
+    // read only after the first stage's barrier B0
+    if (cs.tid < 64) cs.X64[cs.tid] = exp2((double)cs.tid * (1.0 / 64.0));
 #pragma unroll
     for (int t = 0; t < 3 * P; ++t) cs.T[t * Ch::NL + cs.tid] = cs.tab0[t * Ch::NL + cs.tid];
     cs.xg = x.xch + (size_t)bd.first * XREC;
