@@ -37,6 +37,34 @@ _BATCH_SIG = {
 }
 
 
+_SIG = {
+    "ora_tables": (None, [_i, _p, _p, _p, _p, _p]),
+    "ora_op_D": (None, [_i, _d, _p, _i, _i, _p]),
+    "ora_op_KO": (None, [_i, _d, _d, _p, _i, _i, _p]),
+    "ora_op_cell4": (None, [_i, _d, _p, _i, _i, _p]),
+    "ora_constraints": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
+    "ora_rhs": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p]),
+    "ora_evolve": (_i, [_i, _i, _i, _d, _d, _d, _p, _p, _i64, _i64, ctypes.c_int32, _i64, _p,
+                        _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
+    "ora_evolve_scheme": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _p, _p, _p, _i64, _i64, ctypes.c_int32, _i64,
+                               _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
+    "ora_mass_paper": (_d, [_i, _p, _p, _p]),
+    "ora_residuals": (None, [_i, _p, _p, _p, _p, _p, _p]),
+    "ora_adot_residual": (None, [_i, _i, _d, _p, _p, _p, _p]),
+    "ora_jacobi": (_d, [_i, _d, _d, _d]),
+    "ora_modes": (None, [_i, _i, _p, _p]),
+    "ora_spectrum": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
+    "ora_init_gaussian": (None, [_i, _d, _d, _p, _p]),
+    "ora_init_modes": (None, [_i, _d, _i, _p, _p, _p]),
+    "ora_objective": (_i, [_i, _i, _d, _d, _d, _d, _i, _p, _i, _i64, _i64, _p, _p, _p, _p]),
+    "ora_constraints_vjp": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
+    "ora_rhs_vjp": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "ora_step": (None, [_i, _i, _d, _d, _p, _p]),
+    "ora_step_vjp": (None, [_i, _i, _d, _d, _p, _p, _p, _p]),
+    "ora_spectrum_vjp": (None, [_i, _i, _p, _p, _p, _p, _p, _p, _p]),
+}
+
+
 def _bind(lib, sig):
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -53,37 +81,17 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     _bind(lib, _BATCH_SIG)
-    sig = {
-        "ora_tables": (None, [_i, _p, _p, _p, _p, _p]),
-        "ora_op_D": (None, [_i, _d, _p, _i, _i, _p]),
-        "ora_op_KO": (None, [_i, _d, _d, _p, _i, _i, _p]),
-        "ora_op_cell4": (None, [_i, _d, _p, _i, _i, _p]),
-        "ora_constraints": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
-        "ora_rhs": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p]),
-        "ora_evolve": (_i, [_i, _i, _i, _d, _d, _d, _p, _p, _i64, _i64, ctypes.c_int32, _i64, _p,
-                            _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
-        "ora_evolve_scheme": (_i, [_i, _i, _i, _d, _d, _d, _i, _i, _p, _p, _p, _i64, _i64, ctypes.c_int32, _i64,
-                                   _p, _p, _p, ctypes.POINTER(_i64), _p, _p]),
-        "ora_mass_paper": (_d, [_i, _p, _p, _p]),
-        "ora_residuals": (None, [_i, _p, _p, _p, _p, _p, _p]),
-        "ora_adot_residual": (None, [_i, _i, _d, _p, _p, _p, _p]),
-        "ora_jacobi": (_d, [_i, _d, _d, _d]),
-        "ora_modes": (None, [_i, _i, _p, _p]),
-        "ora_spectrum": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
-        "ora_init_gaussian": (None, [_i, _d, _d, _p, _p]),
-        "ora_init_modes": (None, [_i, _d, _i, _p, _p, _p]),
-        "ora_objective": (_i, [_i, _i, _d, _d, _d, _d, _i, _p, _i, _i64, _i64, _p, _p, _p, _p]),
-        "ora_constraints_vjp": (None, [_i, _i, _p, _p, _p, _p, _p, _p]),
-        "ora_rhs_vjp": (None, [_i, _d, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
-        "ora_step": (None, [_i, _i, _d, _d, _p, _p]),
-        "ora_step_vjp": (None, [_i, _i, _d, _d, _p, _p, _p, _p]),
-        "ora_spectrum_vjp": (None, [_i, _i, _p, _p, _p, _p, _p, _p, _p]),
-    }
-    for name, (res, args) in sig.items():
-        f = getattr(lib, name)
-        f.restype = res
-        f.argtypes = args
+    _bind(lib, _SIG)
     _lib = lib
+    return lib
+
+
+def load_library(path):
+    """Another build of the oracle's sources at `path` (say with other compiler
+    flags), with every function bound; pass it as ``lib=`` to :func:`evolve`."""
+    lib = ctypes.CDLL(path)
+    _bind(lib, _BATCH_SIG)
+    _bind(lib, _SIG)
     return lib
 
 
@@ -161,14 +169,15 @@ def rhs(Phi, Pi, A, delta, ko=0.5, frozen=False):
 
 
 def evolve(Phi, Pi, n_stop, n0=0, gauge=GAUGE_BOUNDARY, frozen=False, cfl=0.25, ko=0.5,
-           a_collapse=0.0, snap_every=0, n_slots=0, n_final=None):
+           a_collapse=0.0, snap_every=0, n_slots=0, n_final=None, lib=None):
     """Evolve one instance from step n0 to n_stop (classical RK4, dt = cfl h).
 
     Returns dict with Phi, Pi (state U^n at exit), A, delta, m (its metric),
     steps (n at exit), state, minA, t, t_c and snaps [n_slots, 5, N] when
     snap_every > 0.  State is DONE when n reaches ``n_final`` (default n_stop).
+    ``lib``: another build of the sources (:func:`load_library`).
     """
-    lib = _load()
+    lib = lib or _load()
     Phi, Pi = _f64(Phi).copy(), _f64(Pi).copy()
     N = len(Phi)
     A, delta, m = np.empty(N), np.empty(N), np.empty(N)

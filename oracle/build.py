@@ -21,6 +21,9 @@ COMMON = ["-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
 PARITY_FLAGS = ["-O2"] + COMMON
 TIMING_FLAGS = ["-O3", "-march=native"] + COMMON
+# the self-sensitivity build: the same sources with multiply-adds contracted
+# into FMAs wherever the compiler likes (the host's FMA instructions enabled)
+CONTRACT_FLAGS = ["-O2", "-march=native", "-ffp-contract=fast"] + [f for f in COMMON if f != "-ffp-contract=off"]
 
 
 def _gcc(flags, out, verbose):
@@ -41,6 +44,13 @@ def build_timing(out, verbose=False):
     """The -O3 -march=native timing build, written to `out` (a path outside the
     tree, made on the host that will run it)."""
     return _gcc(TIMING_FLAGS, out, verbose)
+
+
+def build_contract(out, verbose=False):
+    """The sources with FMA contraction on (CONTRACT_FLAGS), written to `out`:
+    how far two roundings of the same arithmetic drift apart bounds how long a
+    parity window can be at a given tolerance."""
+    return _gcc(CONTRACT_FLAGS, out, verbose)
 
 
 if __name__ == "__main__":
